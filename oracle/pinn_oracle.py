@@ -1,0 +1,290 @@
+"""FP64 CPU oracle for one domain-decomposed PINN training step.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this module;
+only the tests, the smoke check and the CPU-baseline leg of the benchmark do.
+
+It computes, from the plain definitions and in float64 (inputs and parameters
+are the float32 values the GPU sees, converted exactly):
+
+* the network of Sec. 3: N^1 = W^1 z + b^1, N^k = W^k tanh(N^{k-1}) + b^k,
+  identity output layer (the adaptive slope n*a^k is fixed at 1);
+* input derivatives of the network output by automatic differentiation, as the
+  paper does for the PDE residual (Sec. 4.1);
+* the residual F = L_x(u) - f of Eq. ProSet for the Poisson, Burgers (Eq. BE)
+  and steady Navier-Stokes (Eq. NSEq) operators;
+* the per-subdomain losses J(Theta_q) of Eq. cPINNLoss (data, residual,
+  average-solution and normal-flux terms) and Eq. XPINNLoss (data, residual,
+  average-solution and residual-continuity terms);
+* the gradient dJ(Theta_q)/dTheta_q with the neighbour's interface values held
+  fixed, as in Algorithm 1 where each rank minimises its own loss using values
+  received from its neighbours;
+* one Adam step per subdomain (Sec. 6; Kingma-Ba form, beta=(0.9,0.999),
+  eps=1e-8);
+* the stitched solution of Eq. FSol with the 1/S indicator on interfaces.
+
+Plain PyTorch CPU ops in float64 serve as the library primitives (matmul, tanh,
+reverse-mode differentiation).  There is no blocking, fusion or reordering.
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+import torch
+
+DT = torch.float64
+
+POISSON2D = "poisson2d"
+BURGERS1D = "burgers1d"
+NS2D = "ns2d_steady"
+
+
+# ----------------------------------------------------------------------------
+# network (Sec. 3)
+
+
+def unpack(theta, widths):
+    """Split a flat parameter vector into [(W^k, b^k)], W^k of shape (N_k, N_{k-1})."""
+    out, off = [], 0
+    for k in range(1, len(widths)):
+        nin, nout = widths[k - 1], widths[k]
+        W = theta[off:off + nout * nin].reshape(nout, nin)
+        off += nout * nin
+        b = theta[off:off + nout]
+        off += nout
+        out.append((W, b))
+    assert off == theta.shape[0], (off, theta.shape)
+    return out
+
+
+def mlp(theta, widths, z):
+    """N^L(z; Theta): tanh on hidden layers, identity on the last one."""
+    layers = unpack(theta, widths)
+    h = z
+    for k, (W, b) in enumerate(layers):
+        a = h @ W.T + b
+        h = torch.tanh(a) if k < len(layers) - 1 else a
+    return h
+
+
+def second_order_set(pde):
+    """Input directions whose pure second derivatives the operator needs."""
+    if pde == BURGERS1D:
+        return (0,)          # u_xx only (inputs are (x, t))
+    return (0, 1)            # Laplacian in (x, y)
+
+
+def input_streams(theta, widths, z, pde, create_graph=True):
+    """u, grad u and the second-order sum  sum_{i in S} d^2 u / dz_i^2  per
+    output component, by reverse-mode automatic differentiation w.r.t. z."""
+    z = z.detach().clone().requires_grad_(True)
+    u = mlp(theta, widths, z)                      # (N, D_o)
+    n_out = u.shape[1]
+    grads, lap = [], []
+    S = second_order_set(pde)
+    for c in range(n_out):
+        g, = torch.autograd.grad(u[:, c].sum(), z, create_graph=True)
+        grads.append(g)
+        acc = torch.zeros_like(u[:, c])
+        for i in S:
+            gi, = torch.autograd.grad(g[:, i].sum(), z, create_graph=True)
+            acc = acc + gi[:, i]
+        lap.append(acc)
+    st = {"u": u, "du": torch.stack(grads, 1), "lap": torch.stack(lap, 1)}
+    if not create_graph:
+        st = {k: v.detach() for k, v in st.items()}
+    return st
+
+
+# ----------------------------------------------------------------------------
+# operators (Eq. ProSet: F = L_x(u) - f)
+
+
+def residual(pde, coef, st, f):
+    """F per residual equation, shape (N, n_eq).
+
+    Poisson:  -Lap u - f.
+    Burgers:  u_t + u u_x - nu u_xx     (inputs (x, t); f = 0).
+    NS:       u u_x + v u_y + p_x - Lap u / Re,
+              u v_x + v v_y + p_y - Lap v / Re,
+              u_x + v_y.
+    """
+    u, du, lap = st["u"], st["du"], st["lap"]
+    if pde == POISSON2D:
+        return (-lap[:, 0] - f[:, 0])[:, None]
+    if pde == BURGERS1D:
+        nu = coef[0]
+        return (du[:, 0, 1] + u[:, 0] * du[:, 0, 0] - nu * lap[:, 0] - f[:, 0])[:, None]
+    if pde == NS2D:
+        re = coef[0]
+        U, V = u[:, 0], u[:, 1]
+        F1 = U * du[:, 0, 0] + V * du[:, 0, 1] + du[:, 2, 0] - lap[:, 0] / re - f[:, 0]
+        F2 = U * du[:, 1, 0] + V * du[:, 1, 1] + du[:, 2, 1] - lap[:, 1] / re - f[:, 1]
+        F3 = du[:, 0, 0] + du[:, 1, 1] - f[:, 2]
+        return torch.stack([F1, F2, F3], 1)
+    raise ValueError(pde)
+
+
+def normal_flux(pde, coef, st, n):
+    """f(u) . n for the conservative form of the equation, shape (N, 1).
+
+    Poisson:  f = -grad u.
+    Burgers:  space-time flux (u^2/2 - nu u_x, u) of u_t + (u^2/2 - nu u_x)_x = 0.
+    """
+    u, du = st["u"], st["du"]
+    if pde == POISSON2D:
+        return (-(n[0] * du[:, 0, 0] + n[1] * du[:, 0, 1]))[:, None]
+    if pde == BURGERS1D:
+        nu = coef[0]
+        fx = 0.5 * u[:, 0] ** 2 - nu * du[:, 0, 0]
+        return (n[0] * fx + n[1] * u[:, 0])[:, None]
+    raise NotImplementedError(f"cPINN flux for {pde}")
+
+
+# ----------------------------------------------------------------------------
+# losses (Eqs. cPINNLoss, XPINNLoss)
+
+
+def _t(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64), dtype=DT)
+
+
+def _mean_sq(x):
+    """(1/N) sum_i sum_c x_ic^2; an empty set contributes 0."""
+    if x.shape[0] == 0:
+        return torch.zeros((), dtype=DT)
+    return (x ** 2).sum() / x.shape[0]
+
+
+def interface_value(prob, q, theta, e, create_graph):
+    """What subdomain q contributes on interface e: u, and flux.n (cPINN) or F (XPINN)."""
+    sd = prob.subdomains[q]
+    z = _t(e.xy)
+    st = input_streams(theta, sd.widths, z, prob.pde, create_graph=create_graph)
+    u = st["u"]
+    if prob.method == "cpinn":
+        other = normal_flux(prob.pde, prob.coef, st, _t(e.normal))
+    else:
+        # the forcing f is the same on both sides of a common point and cancels
+        # in F_q - F_q+; zero is passed so only L_x(u) is compared
+        f0 = torch.zeros((z.shape[0], prob.n_eq), dtype=DT)
+        other = residual(prob.pde, prob.coef, st, f0)
+    return u, other
+
+
+def subdomain_terms(prob, q, thetas, grad_mode="local"):
+    """[J, MSE_u, MSE_F, MSE_uavg, MSE_flux | MSE_R] for subdomain q.
+
+    grad_mode 'local': neighbour values are constants (what each rank sees after
+    the exchange of Algorithm 1).  'sum' keeps neighbours differentiable (used
+    only by tests of the alternative readings)."""
+    sd = prob.subdomains[q]
+    th = thetas[q]
+    Wu, WF, WI, W4 = sd.loss_w
+    # data / boundary term
+    if sd.bnd_xy.shape[0] > 0:
+        ub = mlp(th, sd.widths, _t(sd.bnd_xy))
+        mse_u = _mean_sq(ub - _t(sd.bnd_g))
+    else:
+        mse_u = torch.zeros((), dtype=DT)
+    # residual term
+    if sd.res_xy.shape[0] > 0:
+        st = input_streams(th, sd.widths, _t(sd.res_xy), prob.pde)
+        F = residual(prob.pde, prob.coef, st, _t(sd.res_f))
+        mse_f = _mean_sq(F)
+    else:
+        mse_f = torch.zeros((), dtype=DT)
+    # interface terms, summed over the neighbours q+ of q
+    mse_avg = torch.zeros((), dtype=DT)
+    mse_4 = torch.zeros((), dtype=DT)
+    for e in prob.interfaces:
+        if q not in (e.a, e.b):
+            continue
+        nb = e.b if q == e.a else e.a
+        uq, oq = interface_value(prob, q, th, e, create_graph=True)
+        th_nb = thetas[nb] if grad_mode == "sum" else thetas[nb].detach()
+        un, on = interface_value(prob, nb, th_nb, e, create_graph=(grad_mode == "sum"))
+        uavg = 0.5 * (uq + un)
+        mse_avg = mse_avg + _mean_sq(uq - uavg)
+        mse_4 = mse_4 + _mean_sq(oq - on)
+    J = Wu * mse_u + WF * mse_f + WI * mse_avg + W4 * mse_4
+    return torch.stack([J, mse_u, mse_f, mse_avg, mse_4])
+
+
+def loss_and_grad(prob, params, grad_mode="local"):
+    """Loss terms (n_sd, 5) and per-subdomain gradients dJ_q/dTheta_q (float64)."""
+    thetas = [_t(p).requires_grad_(True) for p in params]
+    terms, grads = [], []
+    for q in range(prob.n_sd):
+        t = subdomain_terms(prob, q, thetas, grad_mode=grad_mode)
+        if grad_mode == "sum":
+            terms.append(t.detach().numpy())
+            grads.append(None)
+            continue
+        g, = torch.autograd.grad(t[0], thetas[q], allow_unused=True)
+        if g is None:
+            g = torch.zeros_like(thetas[q])
+        terms.append(t.detach().numpy())
+        grads.append(g.detach().numpy())
+    return np.stack(terms), grads
+
+
+def grad_of_total(prob, params):
+    """Gradient of sum_r J_r w.r.t. every Theta_q (rejected reading; tests only)."""
+    thetas = [_t(p).requires_grad_(True) for p in params]
+    total = sum(subdomain_terms(prob, q, thetas, grad_mode="sum")[0] for q in range(prob.n_sd))
+    gs = torch.autograd.grad(total, thetas, allow_unused=True)
+    return [(g if g is not None else torch.zeros_like(t)).detach().numpy() for g, t in zip(gs, thetas)]
+
+
+# ----------------------------------------------------------------------------
+# optimiser (Sec. 6)
+
+
+def adam_step(theta, m, v, g, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update; t is the 1-based index of this step."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    theta = theta - lr * mhat / (np.sqrt(vhat) + eps)
+    return theta, m, v
+
+
+def train(prob, params, n_steps, round_to_f32=False):
+    """n_steps of (loss_and_grad, Adam) per subdomain; returns params and loss history."""
+    ps = [np.asarray(p, np.float64) for p in params]
+    ms = [np.zeros_like(p) for p in ps]
+    vs = [np.zeros_like(p) for p in ps]
+    hist = []
+    for t in range(1, n_steps + 1):
+        feed = [p.astype(np.float32) for p in ps] if round_to_f32 else ps
+        terms, grads = loss_and_grad(prob, feed)
+        hist.append(terms)
+        for q in range(prob.n_sd):
+            ps[q], ms[q], vs[q] = adam_step(ps[q], ms[q], vs[q], grads[q], t, prob.subdomains[q].lr)
+    return ps, np.stack(hist)
+
+
+# ----------------------------------------------------------------------------
+# stitched solution (Eq. FSol) and error
+
+
+def eval_stitched(prob, params, xy, owner):
+    """u(z) = sum_q u_q(z) 1_{Omega_q}(z), indicator 1/S on common interfaces.
+
+    owner[i] lists the S subdomains whose closure holds point i (-1 padded)."""
+    xy = np.asarray(xy)
+    out = np.zeros((xy.shape[0], prob.d_out))
+    cnt = (owner >= 0).sum(1)
+    with torch.no_grad():
+        for q in range(prob.n_sd):
+            sel = np.nonzero((owner == q).any(1))[0]
+            if sel.size == 0:
+                continue
+            u = mlp(_t(params[q]), prob.subdomains[q].widths, _t(xy[sel])).numpy()
+            out[sel] += u / cnt[sel][:, None]
+    return out
+
+
+def rel_l2(u, u_exact):
+    return float(np.linalg.norm(u - u_exact) / np.linalg.norm(u_exact))

@@ -1,0 +1,422 @@
+"""Seeded synthetic workloads for domain-decomposed PINN training.
+
+This module only *generates inputs*: subdomain geometry, point sets, forcing
+and target values from closed-form fields, and Glorot-initialised parameters.
+It holds none of the method's arithmetic (no network, residual, loss, gradient
+or optimiser); both the FP64 oracle and the HIP path consume what it returns.
+
+Problem structure follows Sec. 4.2 (non-overlapping subdomains, one network
+each, residual / training / interface point sets per subdomain) and the
+pre-processing stage of Sec. 5.1 (domain split, per-subdomain point sets, an
+edge -> interface-points table). The concrete shapes follow the paper's
+experiments: the 2D Poisson manufactured problem, the 1D viscous Burgers
+equation of Sec. 7.3/7.5 (Eq. BE), and steady incompressible Navier-Stokes
+(Eq. NSEq, Kovasznay closed form standing in for the cavity data), the inverse
+diffusion problem of Sec. 7.6 (Eq. heq) with a seeded star domain and Voronoi
+cells standing in for the US map.
+
+Randomness: numpy PCG64 through ``SeedSequence(seed).spawn(4)``; one stream
+each for geometry, points, parameters and observation noise.  Coordinates and
+targets are produced in float64 and rounded once to float32; everything
+downstream (oracle and GPU) sees the identical float32 values.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+import numpy as np
+
+METHOD_CPINN = "cpinn"
+METHOD_XPINN = "xpinn"
+
+PDE_POISSON2D = "poisson2d"
+PDE_BURGERS1D = "burgers1d"
+PDE_NS2D = "ns2d_steady"
+PDE_DIFFUSION2D_INV = "diffusion2d_inv"
+
+#: number of residual equations / network outputs per PDE
+PDE_NEQ = {PDE_POISSON2D: 1, PDE_BURGERS1D: 1, PDE_NS2D: 3, PDE_DIFFUSION2D_INV: 1}
+PDE_DOUT = {PDE_POISSON2D: 1, PDE_BURGERS1D: 1, PDE_NS2D: 3, PDE_DIFFUSION2D_INV: 1}
+
+
+@dataclass
+class Subdomain:
+    """One subdomain Omega_q with its own network (Sec. 4.2)."""
+    widths: list            # N_0 .. N_L of the solution network
+    loss_w: tuple           # (W_u, W_F, W_I, W_flux | W_IF)  (Eqs. cPINNLoss / XPINNLoss)
+    lr: float               # per-subdomain Adam learning rate (Sec. 6)
+    res_xy: np.ndarray      # (N_F, 2) float32 residual points
+    res_f: np.ndarray       # (N_F, n_eq) float32 forcing f(x) at residual points
+    bnd_xy: np.ndarray      # (N_u, 2) float32 training (boundary/initial/data) points
+    bnd_g: np.ndarray       # (N_u, D_o) float32 targets u^(i)
+    params: np.ndarray      # flat float32, per layer W[out][in] row-major then b[out]
+    # second network (inverse problems only: the unknown coefficient K)
+    aux_widths: list | None = None
+    aux_params: np.ndarray | None = None
+    aux_xy: np.ndarray | None = None     # points with known K values
+    aux_g: np.ndarray | None = None
+
+
+@dataclass
+class Interface:
+    """Common interface between Omega_a and Omega_b with its points (Sec. 5.1)."""
+    a: int
+    b: int
+    xy: np.ndarray          # (N_e, 2) float32
+    normal: np.ndarray      # (2,) float32 unit normal pointing from a to b
+
+
+@dataclass
+class Problem:
+    name: str
+    method: str
+    pde: str
+    coef: tuple             # (nu,) for Burgers, (Re,) for NS, () otherwise
+    subdomains: list
+    interfaces: list
+    eval_xy: np.ndarray = None      # (n, 2) float32 evaluation grid
+    eval_owner: np.ndarray = None   # (n, 4) int32 subdomains containing the point, -1 padded
+    eval_exact: np.ndarray = None   # (n, D_o) float64 exact solution on the grid
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_sd(self):
+        return len(self.subdomains)
+
+    @property
+    def d_out(self):
+        return PDE_DOUT[self.pde]
+
+    @property
+    def n_eq(self):
+        return PDE_NEQ[self.pde]
+
+    def n_residual(self):
+        return int(sum(s.res_xy.shape[0] for s in self.subdomains))
+
+
+# ----------------------------------------------------------------------------
+# parameters
+
+
+def param_count(widths):
+    return int(sum(widths[k] * widths[k - 1] + widths[k] for k in range(1, len(widths))))
+
+
+def glorot_params(rng, widths):
+    """Glorot-normal weights, zero biases, flat canonical layout."""
+    out = []
+    for k in range(1, len(widths)):
+        fan_in, fan_out = widths[k - 1], widths[k]
+        std = math.sqrt(2.0 / (fan_in + fan_out))
+        out.append(rng.normal(0.0, std, size=(fan_out, fan_in)).ravel())
+        out.append(np.zeros(fan_out))
+    return np.concatenate(out).astype(np.float32)
+
+
+def perturb_params(params, seed, scale=0.05):
+    """A seeded relative perturbation, used to test away from initialisation."""
+    rng = np.random.default_rng(seed)
+    p = params.astype(np.float64)
+    return (p + scale * rng.standard_normal(p.shape) * (np.abs(p) + 0.05)).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# closed-form fields
+
+
+def poisson_exact(x, y):
+    return np.sin(np.pi * x) * np.sin(np.pi * y)
+
+
+def poisson_forcing(x, y):
+    # -Lap(sin(pi x) sin(pi y)) = 2 pi^2 sin(pi x) sin(pi y)
+    return 2.0 * np.pi ** 2 * np.sin(np.pi * x) * np.sin(np.pi * y)
+
+
+def kovasznay_lambda(re):
+    return 0.5 * re - math.sqrt(0.25 * re * re + 4.0 * math.pi ** 2)
+
+
+def kovasznay_exact(x, y, re):
+    lam = kovasznay_lambda(re)
+    e = np.exp(lam * x)
+    u = 1.0 - e * np.cos(2 * np.pi * y)
+    v = lam / (2 * np.pi) * e * np.sin(2 * np.pi * y)
+    p = 0.5 * (1.0 - np.exp(2 * lam * x))
+    return np.stack([u, v, p], axis=-1)
+
+
+def diffusion_fields(x, y):
+    """Manufactured u and K for the inverse problem, with f = div(K grad u)."""
+    pi = np.pi
+    u = np.sin(pi * x) * np.sin(pi * y)
+    ux = pi * np.cos(pi * x) * np.sin(pi * y)
+    uy = pi * np.sin(pi * x) * np.cos(pi * y)
+    lap = -2 * pi * pi * u
+    K = 1.0 + 0.5 * np.sin(2 * pi * x) * np.cos(2 * pi * y)
+    Kx = pi * np.cos(2 * pi * x) * np.cos(2 * pi * y)
+    Ky = -pi * np.sin(2 * pi * x) * np.sin(2 * pi * y)
+    f = K * lap + Kx * ux + Ky * uy
+    return u, K, f
+
+
+# ----------------------------------------------------------------------------
+# sampling helpers
+
+
+def _box_points(rng, n, x0, x1, y0, y1):
+    return np.stack([rng.uniform(x0, x1, n), rng.uniform(y0, y1, n)], axis=1)
+
+
+def _segment_points(rng, n, p0, p1):
+    s = rng.uniform(0.0, 1.0, n)
+    p0 = np.asarray(p0, float)
+    p1 = np.asarray(p1, float)
+    return p0[None, :] + s[:, None] * (p1 - p0)[None, :]
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+def _box_grid_problem(name, method, pde, coef, rng_geo, rng_pts, rng_par,
+                      xs, ys, widths_fn, nres_fn, n_bnd_seg, n_iface, exact_fn,
+                      forcing_fn, loss_w, lr, eval_shape):
+    """Cartesian decomposition: boxes [xs[i],xs[i+1]] x [ys[j],ys[j+1]],
+    q = j * nx + i (row-major), Dirichlet data on the outer boundary."""
+    nx, ny = len(xs) - 1, len(ys) - 1
+    d_out = PDE_DOUT[pde]
+    n_eq = PDE_NEQ[pde]
+    subs = []
+    for j in range(ny):
+        for i in range(nx):
+            q = j * nx + i
+            widths = widths_fn(rng_geo, q)
+            n_res = nres_fn(rng_geo, q)
+            x0, x1, y0, y1 = xs[i], xs[i + 1], ys[j], ys[j + 1]
+            res = _box_points(rng_pts, n_res, x0, x1, y0, y1)
+            f = forcing_fn(res[:, 0], res[:, 1]).reshape(n_res, n_eq)
+            segs = []
+            if j == 0:
+                segs.append(((x0, y0), (x1, y0)))
+            if j == ny - 1:
+                segs.append(((x0, y1), (x1, y1)))
+            if i == 0:
+                segs.append(((x0, y0), (x0, y1)))
+            if i == nx - 1:
+                segs.append(((x1, y0), (x1, y1)))
+            bpts = [_segment_points(rng_pts, n_bnd_seg, a, b) for a, b in segs]
+            bnd = np.concatenate(bpts, 0) if bpts else np.zeros((0, 2))
+            g = exact_fn(bnd[:, 0], bnd[:, 1]).reshape(len(bnd), d_out)
+            subs.append(Subdomain(widths=widths, loss_w=tuple(loss_w), lr=lr,
+                                  res_xy=_f32(res), res_f=_f32(f), bnd_xy=_f32(bnd),
+                                  bnd_g=_f32(g), params=glorot_params(rng_par, widths)))
+    ifaces = []
+    for j in range(ny):
+        for i in range(nx):
+            q = j * nx + i
+            if i + 1 < nx:   # vertical edge x = xs[i+1] between q and q+1
+                pts = _segment_points(rng_pts, n_iface, (xs[i + 1], ys[j]), (xs[i + 1], ys[j + 1]))
+                ifaces.append(Interface(q, q + 1, _f32(pts), _f32([1.0, 0.0])))
+            if j + 1 < ny:   # horizontal edge y = ys[j+1] between q and q+nx
+                pts = _segment_points(rng_pts, n_iface, (xs[i], ys[j + 1]), (xs[i + 1], ys[j + 1]))
+                ifaces.append(Interface(q, q + nx, _f32(pts), _f32([0.0, 1.0])))
+    # evaluation grid with the subdomains whose closed box holds each point
+    gx = np.linspace(xs[0], xs[-1], eval_shape[0])
+    gy = np.linspace(ys[0], ys[-1], eval_shape[1])
+    X, Y = np.meshgrid(gx, gy, indexing="ij")
+    exy = np.stack([X.ravel(), Y.ravel()], 1)
+    exy32 = _f32(exy)
+    ex = exy32.astype(np.float64)
+    owner = -np.ones((len(ex), 4), np.int32)
+    cnt = np.zeros(len(ex), np.int32)
+    for j in range(ny):
+        for i in range(nx):
+            q = j * nx + i
+            inside = ((ex[:, 0] >= xs[i]) & (ex[:, 0] <= xs[i + 1]) &
+                      (ex[:, 1] >= ys[j]) & (ex[:, 1] <= ys[j + 1]))
+            idx = np.nonzero(inside)[0]
+            owner[idx, cnt[idx]] = q
+            cnt[idx] += 1
+    exact = exact_fn(ex[:, 0], ex[:, 1]).reshape(len(ex), d_out)
+    return Problem(name=name, method=method, pde=pde, coef=tuple(coef), subdomains=subs,
+                   interfaces=ifaces, eval_xy=exy32, eval_owner=owner, eval_exact=exact)
+
+
+# ----------------------------------------------------------------------------
+# the five workloads
+
+
+def _streams(seed):
+    ss = np.random.SeedSequence(seed).spawn(4)
+    return [np.random.default_rng(s) for s in ss]
+
+
+def c1_cpinn_poisson(seed=0, scale=1.0):
+    """cPINN, -Lap u = f on [0,1]^2 with u = sin(pi x) sin(pi y), 2x2 boxes,
+    nets 2-20-20-20-1, 1000 residual points per box, 50 boundary points per
+    outer edge segment, 100 points per interface."""
+    g, p, w, _ = _streams(seed)
+    n_res = max(1, int(round(1000 * scale)))
+    n_b = max(1, int(round(50 * scale)))
+    n_i = max(1, int(round(100 * scale)))
+    return _box_grid_problem(
+        "c1_cpinn_poisson", METHOD_CPINN, PDE_POISSON2D, (), g, p, w,
+        [0.0, 0.5, 1.0], [0.0, 0.5, 1.0],
+        lambda r, q: [2, 20, 20, 20, 1], lambda r, q: n_res, n_b, n_i,
+        poisson_exact, poisson_forcing, (1.0, 1.0, 1.0, 1.0), 1e-3, (201, 201))
+
+
+def c2_xpinn_poisson(seed=0, scale=1.0):
+    """XPINN, same Poisson problem on 4x4 boxes of side 0.25; per subdomain a
+    width from {20,40,60,80}, 3..6 hidden layers, and U_int[2000,20000]
+    residual points; 50 boundary points per outer segment, 200 per interface."""
+    g, p, w, _ = _streams(seed)
+
+    def widths(r, q):
+        wd = int(r.choice([20, 40, 60, 80]))
+        depth = int(r.integers(3, 7))
+        return [2] + [wd] * depth + [1]
+
+    def nres(r, q):
+        return max(1, int(round(int(r.integers(2000, 20001)) * scale)))
+
+    n_b = max(1, int(round(50 * scale)))
+    n_i = max(1, int(round(200 * scale)))
+    cuts = [0.0, 0.25, 0.5, 0.75, 1.0]
+    return _box_grid_problem(
+        "c2_xpinn_poisson", METHOD_XPINN, PDE_POISSON2D, (), g, p, w, cuts, cuts,
+        widths, nres, n_b, n_i, poisson_exact, poisson_forcing,
+        (1.0, 1.0, 1.0, 1.0), 1e-3, (201, 201))
+
+
+def c3_cpinn_burgers(seed=0, scale=1.0, n_strips=8):
+    """cPINN, u_t + u u_x = nu u_xx, nu = 0.01/pi, x in [-1,1], t in [0,1],
+    u(0,x) = -sin(pi x), u(t,+-1) = 0; n_strips spatial strips; nets
+    2-50x6-1; 5000 residual, 256 initial, 100 boundary (end strips) and
+    200 interface points.  Inputs are (x, t)."""
+    g, p, w, _ = _streams(seed)
+    nu = 0.01 / math.pi
+    xs = np.linspace(-1.0, 1.0, n_strips + 1)
+    n_res = max(1, int(round(5000 * scale)))
+    n_ic = max(1, int(round(256 * scale)))
+    n_bc = max(1, int(round(100 * scale)))
+    n_i = max(1, int(round(200 * scale)))
+    subs = []
+    for q in range(n_strips):
+        widths = [2] + [50] * 6 + [1]
+        x0, x1 = xs[q], xs[q + 1]
+        res = _box_points(p, n_res, x0, x1, 0.0, 1.0)
+        ic = np.stack([p.uniform(x0, x1, n_ic), np.zeros(n_ic)], 1)
+        parts = [ic]
+        targets = [-np.sin(np.pi * ic[:, 0])]
+        if q == 0:
+            bc = np.stack([np.full(n_bc, -1.0), p.uniform(0.0, 1.0, n_bc)], 1)
+            parts.append(bc)
+            targets.append(np.zeros(n_bc))
+        if q == n_strips - 1:
+            bc = np.stack([np.full(n_bc, 1.0), p.uniform(0.0, 1.0, n_bc)], 1)
+            parts.append(bc)
+            targets.append(np.zeros(n_bc))
+        bnd = np.concatenate(parts, 0)
+        gv = np.concatenate(targets, 0)[:, None]
+        subs.append(Subdomain(widths=widths, loss_w=(1.0, 1.0, 1.0, 1.0), lr=1e-3,
+                              res_xy=_f32(res), res_f=_f32(np.zeros((n_res, 1))),
+                              bnd_xy=_f32(bnd), bnd_g=_f32(gv),
+                              params=glorot_params(w, widths)))
+    ifaces = []
+    for q in range(n_strips - 1):
+        pts = np.stack([np.full(n_i, xs[q + 1]), p.uniform(0.0, 1.0, n_i)], 1)
+        ifaces.append(Interface(q, q + 1, _f32(pts), _f32([1.0, 0.0])))
+    # evaluation grid 256 x 101 in (x, t); owners from the strips
+    gx = np.linspace(-1.0, 1.0, 256)
+    gt = np.linspace(0.0, 1.0, 101)
+    X, T = np.meshgrid(gx, gt, indexing="ij")
+    exy32 = _f32(np.stack([X.ravel(), T.ravel()], 1))
+    ex = exy32.astype(np.float64)
+    owner = -np.ones((len(ex), 4), np.int32)
+    cnt = np.zeros(len(ex), np.int32)
+    for q in range(n_strips):
+        idx = np.nonzero((ex[:, 0] >= xs[q]) & (ex[:, 0] <= xs[q + 1]))[0]
+        owner[idx, cnt[idx]] = q
+        cnt[idx] += 1
+    exact = burgers_exact(ex[:, 0], ex[:, 1], nu)[:, None]
+    return Problem(name="c3_cpinn_burgers", method=METHOD_CPINN, pde=PDE_BURGERS1D,
+                   coef=(nu,), subdomains=subs, interfaces=ifaces, eval_xy=exy32,
+                   eval_owner=owner, eval_exact=exact)
+
+
+def burgers_exact(x, t, nu, n_nodes=120):
+    """Reference solution of the viscous Burgers problem with u0 = -sin(pi x)
+    through the Cole-Hopf representation, evaluated by Gauss-Hermite
+    quadrature (only used for the reported relative L2 error)."""
+    x = np.asarray(x, float)
+    t = np.asarray(t, float)
+    out = np.empty_like(x)
+    z, wq = np.polynomial.hermite.hermgauss(n_nodes)
+    t0 = t <= 0
+    out[t0] = -np.sin(np.pi * x[t0])
+    xx = x[~t0][:, None]
+    tt = t[~t0][:, None]
+    s = np.sqrt(4.0 * nu * tt)
+    y = xx - s * z[None, :]
+    # phi(y) = exp(-cos(pi y) / (2 pi nu)); shift the exponent for stability
+    expo = -np.cos(np.pi * y) / (2 * np.pi * nu)
+    m = expo.max(axis=1, keepdims=True)
+    e = np.exp(expo - m) * wq[None, :]
+    num = (np.sin(np.pi * y) * e).sum(1)
+    den = e.sum(1)
+    out[~t0] = -num / den
+    return out
+
+
+def c4_xpinn_kovasznay(seed=0, scale=1.0, re=40.0):
+    """XPINN, steady NS (Eq. NSEq) at Re = 40 with the Kovasznay closed form on
+    [-0.5,1] x [-0.5,1.5], 3x3 subdomains, nets 2-60x5-3, 10k residual points
+    each, 100 exact (u,v,p) points per outer segment, 200 per interface."""
+    g, p, w, _ = _streams(seed)
+    n_res = max(1, int(round(10000 * scale)))
+    n_b = max(1, int(round(100 * scale)))
+    n_i = max(1, int(round(200 * scale)))
+    return _box_grid_problem(
+        "c4_xpinn_kovasznay", METHOD_XPINN, PDE_NS2D, (re,), g, p, w,
+        [-0.5, 0.0, 0.5, 1.0], [-0.5, 1.0 / 6.0, 5.0 / 6.0, 1.5],
+        lambda r, q: [2] + [60] * 5 + [3], lambda r, q: n_res, n_b, n_i,
+        lambda x, y: kovasznay_exact(x, y, re), lambda x, y: np.zeros((len(x), 3)),
+        (1.0, 1.0, 1.0, 1.0), 1e-3, (151, 201))
+
+
+WORKLOADS = {
+    "c1_cpinn_poisson": c1_cpinn_poisson,
+    "c2_xpinn_poisson": c2_xpinn_poisson,
+    "c3_cpinn_burgers": c3_cpinn_burgers,
+    "c4_xpinn_kovasznay": c4_xpinn_kovasznay,
+}
+
+
+def make_problem(name, seed=0, scale=1.0, **kw):
+    return WORKLOADS[name](seed=seed, scale=scale, **kw)
+
+
+def custom_box_problem(method, pde, nx, ny, widths_list, n_res_list, n_bnd_seg, n_iface,
+                       seed=0, coef=(), loss_w=(1.0, 1.0, 1.0, 1.0), lr=1e-3,
+                       domain=(0.0, 1.0, 0.0, 1.0)):
+    """Small custom Cartesian problems for tests (ragged counts, mixed widths)."""
+    g, p, w, _ = _streams(seed)
+    xs = list(np.linspace(domain[0], domain[1], nx + 1))
+    ys = list(np.linspace(domain[2], domain[3], ny + 1))
+    if pde == PDE_POISSON2D:
+        ex, fo = poisson_exact, poisson_forcing
+    elif pde == PDE_NS2D:
+        re = coef[0]
+        ex = lambda x, y: kovasznay_exact(x, y, re)
+        fo = lambda x, y: np.zeros((len(x), 3))
+    elif pde == PDE_BURGERS1D:
+        ex = lambda x, y: -np.sin(np.pi * x) * (y == 0)
+        fo = lambda x, y: np.zeros(len(x))
+    else:
+        raise ValueError(pde)
+    return _box_grid_problem("custom", method, pde, coef, g, p, w, xs, ys,
+                             lambda r, q: list(widths_list[q]), lambda r, q: int(n_res_list[q]),
+                             n_bnd_seg, n_iface, ex, fo, loss_w, lr, (21, 21))

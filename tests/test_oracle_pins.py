@@ -1,0 +1,334 @@
+"""Pins of the FP64 oracle against mathematics it does not itself compute:
+finite differences, closed forms, exact solutions, invariants and a library
+optimiser.  A dropped term, a wrong sign or index in the oracle fails one of
+these."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import pinn_oracle as O
+from paper_2104_10013_amd import workloads as W
+
+DT = torch.float64
+
+
+def _rand_theta(rng, widths, scale=1.0):
+    p = W.glorot_params(rng, widths).astype(np.float64)
+    # non-zero biases so every parameter is exercised
+    off = 0
+    for k in range(1, len(widths)):
+        off += widths[k] * widths[k - 1]
+        p[off:off + widths[k]] = rng.normal(0, 0.3, widths[k])
+        off += widths[k]
+    return torch.tensor(p * scale, dtype=DT)
+
+
+# --------------------------------------------------------------------------
+# input derivatives (Taylor quantities) vs central finite differences
+
+
+@pytest.mark.parametrize("widths,pde", [([2, 5, 5, 1], "poisson2d"), ([2, 4, 6, 4, 3], "ns2d_steady"),
+                                        ([2, 5, 5, 1], "burgers1d")])
+def test_input_streams_vs_central_fd(widths, pde):
+    rng = np.random.default_rng(1)
+    th = _rand_theta(rng, widths)
+    z = torch.tensor(rng.uniform(-1, 1, (7, 2)), dtype=DT)
+    st = O.input_streams(th, widths, z, pde, create_graph=False)
+    f = lambda zz: O.mlp(th, widths, zz).detach()
+    h1, h2 = 1e-5, 1e-3
+    S = O.second_order_set(pde)
+    lap = torch.zeros_like(st["lap"])
+    for i in range(2):
+        e = torch.zeros(2, dtype=DT)
+        e[i] = 1
+        dfd = (f(z + h1 * e) - f(z - h1 * e)) / (2 * h1)
+        assert torch.allclose(st["du"][:, :, i], dfd, rtol=1e-7, atol=1e-8)
+        if i in S:
+            lap += (f(z + h2 * e) - 2 * f(z) + f(z - h2 * e)) / (h2 * h2)
+    assert torch.allclose(st["lap"], lap, rtol=1e-5, atol=1e-6)
+
+
+def test_one_neuron_closed_form():
+    # u = c tanh(w1 x + w2 y + b) + d
+    w1, w2, b, c, d = 0.7, -1.3, 0.2, 1.9, -0.4
+    th = torch.tensor([w1, w2, b, c, d], dtype=DT)
+    z = torch.tensor([[0.3, 0.1], [-0.5, 0.8], [1.2, -0.7]], dtype=DT)
+    st = O.input_streams(th, [2, 1, 1], z, "poisson2d", create_graph=False)
+    a = w1 * z[:, 0] + w2 * z[:, 1] + b
+    t = torch.tanh(a)
+    s1 = 1 / torch.cosh(a) ** 2
+    assert torch.allclose(st["u"][:, 0], c * t + d, rtol=1e-14)
+    assert torch.allclose(st["du"][:, 0, 0], c * s1 * w1, rtol=1e-13)
+    assert torch.allclose(st["du"][:, 0, 1], c * s1 * w2, rtol=1e-13)
+    lap = c * (-2 * t * s1) * (w1 ** 2 + w2 ** 2)
+    assert torch.allclose(st["lap"][:, 0], lap, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# residual operators: exact solutions give F == 0
+
+
+def _pts(n=50, seed=3, lo=0.0, hi=1.0):
+    return np.random.default_rng(seed).uniform(lo, hi, (n, 2))
+
+
+def test_poisson_exact_solution_zero_residual():
+    p = _pts()
+    x, y = p[:, 0], p[:, 1]
+    pi = math.pi
+    st = {"u": torch.tensor(np.sin(pi * x) * np.sin(pi * y))[:, None],
+          "du": torch.tensor(np.stack([pi * np.cos(pi * x) * np.sin(pi * y),
+                                       pi * np.sin(pi * x) * np.cos(pi * y)], 1))[:, None, :],
+          "lap": torch.tensor(-2 * pi * pi * np.sin(pi * x) * np.sin(pi * y))[:, None]}
+    f = torch.tensor(W.poisson_forcing(x, y))[:, None]
+    F = O.residual("poisson2d", (), st, f)
+    assert F.abs().max() < 1e-12
+
+
+def test_kovasznay_exact_solution_zero_residual():
+    re = 40.0
+    lam = W.kovasznay_lambda(re)
+    p = _pts(lo=-0.5, hi=1.0)
+    x, y = p[:, 0], p[:, 1]
+    e = np.exp(lam * x)
+    c, s = np.cos(2 * np.pi * y), np.sin(2 * np.pi * y)
+    k = 2 * np.pi
+    u = 1 - e * c
+    v = lam / k * e * s
+    pr = 0.5 * (1 - e * e)
+    ux, uy = -lam * e * c, k * e * s
+    vx, vy = lam * lam / k * e * s, lam * e * c
+    px, py = -lam * e * e, 0 * x
+    lapu = -(lam * lam - k * k) * e * c
+    lapv = lam / k * (lam * lam - k * k) * e * s
+    st = {"u": torch.tensor(np.stack([u, v, pr], 1)),
+          "du": torch.tensor(np.stack([np.stack([ux, uy], 1), np.stack([vx, vy], 1),
+                                       np.stack([px, py], 1)], 1)),
+          "lap": torch.tensor(np.stack([lapu, lapv, 0 * x], 1))}
+    F = O.residual("ns2d_steady", (re,), st, torch.zeros(len(x), 3, dtype=DT))
+    assert F.abs().max() < 1e-12
+    # and the closed form of the workload matches these fields
+    np.testing.assert_allclose(W.kovasznay_exact(x, y, re), np.stack([u, v, pr], 1), rtol=1e-14)
+
+
+def test_burgers_travelling_wave_zero_residual():
+    # u = c - a tanh(a (x - c t) / (2 nu)) solves u_t + u u_x = nu u_xx
+    nu, a, c = 0.05, 0.8, 0.3
+    p = _pts(lo=-1, hi=1)
+    x, t = p[:, 0], p[:, 1]
+    xi = a * (x - c * t) / (2 * nu)
+    th, sech2 = np.tanh(xi), 1 / np.cosh(xi) ** 2
+    u = c - a * th
+    ux = -a * a / (2 * nu) * sech2
+    ut = -c * ux
+    uxx = a ** 3 / (2 * nu * nu) * th * sech2
+    st = {"u": torch.tensor(u)[:, None], "du": torch.tensor(np.stack([ux, ut], 1))[:, None, :],
+          "lap": torch.tensor(uxx)[:, None]}
+    F = O.residual("burgers1d", (nu,), st, torch.zeros(len(x), 1, dtype=DT))
+    assert F.abs().max() < 1e-10
+
+
+def test_poisson_flux_and_burgers_flux_closed_form():
+    st = {"u": torch.tensor([[0.5]], dtype=DT), "du": torch.tensor([[[2.0, -3.0]]], dtype=DT),
+          "lap": torch.zeros(1, 1, dtype=DT)}
+    n = torch.tensor([0.6, 0.8], dtype=DT)
+    assert float(O.normal_flux("poisson2d", (), st, n)) == pytest.approx(-(0.6 * 2 - 0.8 * 3))
+    nu = 0.1
+    got = float(O.normal_flux("burgers1d", (nu,), st, torch.tensor([1.0, 0.0], dtype=DT)))
+    assert got == pytest.approx(0.5 * 0.25 - nu * 2.0)
+
+
+# --------------------------------------------------------------------------
+# loss assembly
+
+
+def test_zero_network_gives_mean_forcing_squared():
+    prob = W.c1_cpinn_poisson(seed=0)
+    params = [np.zeros_like(s.params) for s in prob.subdomains]
+    terms, grads = O.loss_and_grad(prob, params)
+    for q, s in enumerate(prob.subdomains):
+        f = s.res_f.astype(np.float64)[:, 0]
+        g = s.bnd_g.astype(np.float64)[:, 0]
+        assert terms[q, 2] == pytest.approx(np.mean(f * f), rel=1e-13)
+        assert terms[q, 1] == pytest.approx(np.mean(g * g), abs=1e-15)
+        assert terms[q, 3] == 0 and terms[q, 4] == 0
+    # Monte Carlo estimate of E[f^2] = pi^4 over the unit square
+    allf = np.concatenate([s.res_f[:, 0] for s in prob.subdomains]).astype(np.float64)
+    assert np.mean(allf ** 2) == pytest.approx(math.pi ** 4, rel=0.05)
+
+
+def _two_box(method="xpinn", seed=0, n_res=40, widths=(2, 6, 6, 1)):
+    return W.custom_box_problem(method, "poisson2d", 2, 1, [list(widths)] * 2, [n_res, n_res + 3],
+                                n_bnd_seg=9, n_iface=11, seed=seed)
+
+
+@pytest.mark.parametrize("method", ["cpinn", "xpinn"])
+def test_identical_networks_zero_interface_terms(method):
+    prob = _two_box(method)
+    p = prob.subdomains[0].params
+    terms, grads = O.loss_and_grad(prob, [p, p.copy()])
+    assert terms[0, 3] == 0 and terms[0, 4] == 0 and terms[1, 3] == 0 and terms[1, 4] == 0
+    # the gradient then equals that of the data and residual terms alone
+    prob2 = _two_box(method)
+    for s in prob2.subdomains:
+        s.loss_w = (1.0, 1.0, 0.0, 0.0)
+    _, g2 = O.loss_and_grad(prob2, [p, p.copy()])
+    for q in range(2):
+        np.testing.assert_allclose(grads[q], g2[q], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("method", ["cpinn", "xpinn"])
+def test_interface_terms_symmetric(method):
+    prob = _two_box(method)
+    terms, _ = O.loss_and_grad(prob, [s.params for s in prob.subdomains])
+    assert terms[0, 3] == pytest.approx(terms[1, 3], rel=1e-14)
+    assert terms[0, 4] == pytest.approx(terms[1, 4], rel=1e-14)
+    assert terms[0, 3] > 0 and terms[0, 4] > 0
+    # J is the weighted sum of its terms
+    for q in range(2):
+        assert terms[q, 0] == pytest.approx(terms[q, 1:].sum(), rel=1e-14)
+
+
+def test_uavg_term_is_quarter_of_squared_jump():
+    # |u_q - (u_q + u_q+)/2|^2 = (u_q - u_q+)^2 / 4, averaged over the N_e points
+    prob = _two_box("xpinn")
+    params = [s.params for s in prob.subdomains]
+    e = prob.interfaces[0]
+    ua = O.mlp(torch.tensor(params[0], dtype=DT), prob.subdomains[0].widths, torch.tensor(e.xy, dtype=DT))
+    ub = O.mlp(torch.tensor(params[1], dtype=DT), prob.subdomains[1].widths, torch.tensor(e.xy, dtype=DT))
+    ref = float(((ua - ub) ** 2).mean()) / 4
+    terms, _ = O.loss_and_grad(prob, params)
+    assert terms[0, 3] == pytest.approx(ref, rel=1e-13)
+
+
+# --------------------------------------------------------------------------
+# gradient
+
+
+def _fd_grad(prob, params, q, h=1e-6, idx=None):
+    base = [np.asarray(p, np.float64) for p in params]
+    n = base[q].size
+    idx = range(n) if idx is None else idx
+    g = np.zeros(n)
+    for i in idx:
+        pp = [b.copy() for b in base]
+        pm = [b.copy() for b in base]
+        pp[q][i] += h
+        pm[q][i] -= h
+        thp = [torch.tensor(x, dtype=DT) for x in pp]
+        thm = [torch.tensor(x, dtype=DT) for x in pm]
+        jp = float(O.subdomain_terms(prob, q, thp)[0])
+        jm = float(O.subdomain_terms(prob, q, thm)[0])
+        g[i] = (jp - jm) / (2 * h)
+    return g
+
+
+@pytest.mark.parametrize("method", ["cpinn", "xpinn"])
+def test_gradient_vs_central_fd_poisson(method):
+    prob = W.custom_box_problem(method, "poisson2d", 2, 1, [[2, 3, 3, 1], [2, 3, 3, 1]], [13, 9],
+                                n_bnd_seg=5, n_iface=7, seed=4)
+    params = [W.perturb_params(s.params, 9, 0.3) for s in prob.subdomains]
+    _, grads = O.loss_and_grad(prob, params)
+    for q in range(2):
+        fd = _fd_grad(prob, params, q)
+        np.testing.assert_allclose(grads[q], fd, rtol=2e-6, atol=1e-8)
+
+
+def test_gradient_vs_central_fd_ns_and_burgers():
+    prob = W.custom_box_problem("xpinn", "ns2d_steady", 2, 1, [[2, 3, 3, 3], [2, 4, 3]], [8, 6],
+                                n_bnd_seg=4, n_iface=5, seed=5, coef=(40.0,), domain=(-0.5, 1.0, -0.5, 1.5))
+    params = [W.perturb_params(s.params, 2, 0.3) for s in prob.subdomains]
+    _, grads = O.loss_and_grad(prob, params)
+    for q in range(2):
+        np.testing.assert_allclose(grads[q], _fd_grad(prob, params, q), rtol=2e-6, atol=1e-8)
+    prob = W.c3_cpinn_burgers(seed=1, scale=0.004, n_strips=2)
+    for s in prob.subdomains:
+        s.widths = [2, 3, 3, 1]
+        s.params = W.glorot_params(np.random.default_rng(0), s.widths)
+    params = [W.perturb_params(s.params, 3, 0.3) for s in prob.subdomains]
+    _, grads = O.loss_and_grad(prob, params)
+    for q in range(2):
+        np.testing.assert_allclose(grads[q], _fd_grad(prob, params, q), rtol=2e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("method", ["cpinn", "xpinn"])
+def test_local_gradient_vs_gradient_of_total(method):
+    """grad_q sum_r J_r = grad_q J_q + (interface part of grad_q J_q) under
+    equal weights: separates the paper's per-subdomain reading from grad(sum)."""
+    prob = _two_box(method, seed=2)
+    params = [W.perturb_params(s.params, 1, 0.2) for s in prob.subdomains]
+    _, g_local = O.loss_and_grad(prob, params)
+    g_total = O.grad_of_total(prob, params)
+    prob_i = _two_box(method, seed=2)
+    for s in prob_i.subdomains:
+        s.loss_w = (0.0, 0.0, 1.0, 1.0)
+    _, g_iface = O.loss_and_grad(prob_i, params)
+    for q in range(2):
+        np.testing.assert_allclose(g_total[q], g_local[q] + g_iface[q], rtol=1e-10, atol=1e-13)
+        assert np.linalg.norm(g_iface[q]) > 1e-6
+
+
+# --------------------------------------------------------------------------
+# Adam
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(0)
+    th, g = rng.normal(size=20), rng.normal(size=20)
+    lr = 1e-3
+    th1, m, v = O.adam_step(th, np.zeros(20), np.zeros(20), g, 1, lr)
+    np.testing.assert_allclose(th1, th - lr * g / (np.abs(g) + 1e-8), rtol=1e-15, atol=1e-18)
+
+
+def test_adam_matches_torch_optim():
+    rng = np.random.default_rng(1)
+    th = rng.normal(size=30)
+    p = torch.tensor(th.copy(), dtype=DT, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(30)
+    v = np.zeros(30)
+    for t in range(1, 8):
+        g = rng.normal(size=30)
+        p.grad = torch.tensor(g, dtype=DT)
+        opt.step()
+        th, m, v = O.adam_step(th, m, v, g, t, 3e-3)
+    np.testing.assert_allclose(th, p.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# stitched solution
+
+
+def test_stitched_eval_averages_on_interfaces():
+    prob = W.c1_cpinn_poisson(seed=0, scale=0.05)
+    params = [s.params for s in prob.subdomains]
+    xy = np.array([[0.25, 0.25], [0.5, 0.25], [0.5, 0.5], [0.75, 0.9]], np.float32)
+    owner = np.array([[0, -1, -1, -1], [0, 1, -1, -1], [0, 1, 2, 3], [3, -1, -1, -1]], np.int32)
+    u = O.eval_stitched(prob, params, xy, owner)
+    ind = [O.mlp(torch.tensor(p, dtype=DT), s.widths, torch.tensor(xy, dtype=DT)).numpy()[:, 0]
+           for p, s in zip(params, prob.subdomains)]
+    assert u[0, 0] == pytest.approx(ind[0][0])
+    assert u[1, 0] == pytest.approx(0.5 * (ind[0][1] + ind[1][1]))
+    assert u[2, 0] == pytest.approx(0.25 * sum(ind[k][2] for k in range(4)))
+    assert u[3, 0] == pytest.approx(ind[3][3])
+    # the workload's owner table marks the centre cross point with all 4 boxes
+    i = np.nonzero((np.abs(prob.eval_xy[:, 0] - 0.5) < 1e-7) & (np.abs(prob.eval_xy[:, 1] - 0.5) < 1e-7))[0]
+    assert len(i) == 1 and (prob.eval_owner[i[0]] >= 0).sum() == 4
+
+
+def test_burgers_reference_solution():
+    nu = 0.01 / math.pi
+    x = np.linspace(-1, 1, 9)
+    np.testing.assert_allclose(W.burgers_exact(x, np.zeros_like(x), nu), -np.sin(np.pi * x), atol=1e-15)
+    # boundary values stay 0 and quadrature has converged
+    t = np.full(3, 0.5)
+    xb = np.array([-1.0, 0.37, 1.0])
+    u1 = W.burgers_exact(xb, t, nu, n_nodes=120)
+    u2 = W.burgers_exact(xb, t, nu, n_nodes=240)
+    assert abs(u1[0]) < 1e-10 and abs(u1[2]) < 1e-10
+    np.testing.assert_allclose(u1, u2, atol=1e-8)
+    # odd symmetry u(-x,t) = -u(x,t)
+    np.testing.assert_allclose(W.burgers_exact(-xb, t, nu), -u1, atol=1e-10)
