@@ -1,0 +1,166 @@
+/*
+ * ddpinn.h -- C ABI of libddpinn, the MI355X (gfx950) training step of
+ * domain-decomposed physics-informed neural networks (cPINN and XPINN).
+ *
+ * Problem statement (Sec. 4.2): the domain is split into N_sd non-overlapping
+ * subdomains Omega_q, each with its own fully connected tanh network (Sec. 3,
+ * identity output layer) and its own width and depth.  Each subdomain has
+ * residual points x_F, training (boundary / initial / data) points x_u, and
+ * shares interface points x_I with each neighbour q+.  One training step
+ * (Algorithm 1) evaluates every network at its points together with the input
+ * derivatives the PDE needs, forms the subdomain loss J(Theta_q) of
+ * Eq. cPINNLoss or Eq. XPINNLoss, differentiates it with respect to Theta_q
+ * with the neighbour's interface values held fixed, and applies one Adam
+ * update per subdomain (Sec. 6).
+ *
+ * Conventions shared by every call:
+ *  - Return value: DDP_OK (0) on success, a negative DDP_E* code otherwise;
+ *    ddp_last_error() then returns a thread-local message.  No C++ exception
+ *    crosses this interface.
+ *  - Ownership: every input array is copied by the library (at the call, or
+ *    at ddp_finalize for topology data); the caller keeps its buffers.
+ *    Output arrays are owned by the caller.
+ *  - "on_device" = 1 means the pointer is HIP device memory, 0 host memory.
+ *  - Asynchrony: after ddp_finalize every call that launches work is
+ *    stream-ordered on the stream given to ddp_finalize and returns without
+ *    waiting; ddp_sync() waits and reports non-finite losses.
+ *  - Parameters of one network use the canonical flat layout: for each layer
+ *    k = 1..L, W^k as [N_k][N_{k-1}] row-major followed by b^k[N_k].
+ *  - A handle is not thread-safe; use one handle per thread.
+ */
+#ifndef DDPINN_H
+#define DDPINN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddp_problem ddp_problem; /* opaque, owned by the library */
+
+enum {
+  DDP_OK = 0,
+  DDP_EINVAL = -1,     /* invalid argument or unsupported combination */
+  DDP_ENOMEM = -2,     /* host or device allocation failed */
+  DDP_EHIP = -3,       /* a HIP runtime call failed */
+  DDP_ESTATE = -4,     /* call not valid in the handle's current state */
+  DDP_ENONFINITE = -5  /* a loss computed since the last sync was NaN or inf */
+};
+
+/* Algorithm 1 selects the interface condition: cPINN (normal-flux continuity)
+ * or XPINN (residual continuity); both add average-solution continuity. */
+enum { DDP_CPINN = 0, DDP_XPINN = 1 };
+
+/* Operators L_x of Eq. ProSet (F = L_x(u) - f):
+ *  POISSON2D    -Lap u = f, inputs (x, y), one output.
+ *  BURGERS1D    u_t + u u_x - nu u_xx = f (Eq. BE), inputs (x, t), coef[0] = nu.
+ *  NS2D_STEADY  steady incompressible Navier-Stokes (Eq. NSEq), inputs (x, y),
+ *               outputs (u, v, p), coef[0] = Re; three residual equations. */
+enum { DDP_POISSON2D = 0, DDP_BURGERS1D = 1, DDP_NS2D_STEADY = 2 };
+
+/* point kinds for ddp_set_points */
+enum { DDP_RESIDUAL = 0, DDP_DATA = 1 };
+
+/* tuning options (ddp_set_option), all optional */
+enum {
+  DDP_OPT_CHUNK_POINTS = 0, /* points per work item (multiple of the tile) */
+  DDP_OPT_BLOCKS_PER_CU = 1 /* persistent workgroups per compute unit (1 or 2) */
+};
+
+/* Create an empty problem.  coef holds n_coef operator constants (see the
+ * operator list above).  method is DDP_CPINN or DDP_XPINN. */
+int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n_coef);
+
+/* Add subdomain Omega_q with its network (Sec. 3).  n_nets must be 1.
+ * n_layers[0] = L + 1 entries of widths = N_0..N_L with N_0 = 2, N_L = number
+ * of PDE outputs, hidden widths equal and at most 112, 1..8 hidden layers.
+ * loss_w = (W_u, W_F, W_I, W_flux for cPINN | W_IF for XPINN) of Eq. cPINNLoss
+ * / Eq. XPINNLoss.  lr is this subdomain's Adam learning rate.  *sd_id
+ * receives q (0-based, in call order). */
+int ddp_add_subdomain(ddp_problem* p, int n_nets, const int* n_layers, const int* widths,
+                      const float* loss_w, float lr, int* sd_id);
+
+/* Set the residual points {x_F} (kind DDP_RESIDUAL; val = forcing f(x), n x
+ * n_eq) or training points {x_u} (kind DDP_DATA; val = targets u^(i), n x
+ * N_L) of subdomain sd.  xy is n x 2 interleaved.  Replaces earlier points of
+ * that kind.  Non-finite values are rejected.  Valid before ddp_finalize. */
+int ddp_set_points(ddp_problem* p, int sd, int kind, int n, const float* xy, const float* val,
+                   int on_device);
+
+/* Add a common interface between sd_a and sd_b (a != b) with n points (n x 2)
+ * and unit normal (pointing from a to b) used by the cPINN flux term.  Both
+ * networks are evaluated at the same points.  *if_id receives its index. */
+int ddp_add_interface(ddp_problem* p, int sd_a, int sd_b, int n, const float* xy,
+                      const float normal[2], int on_device, int* if_id);
+
+/* Set a tuning option (see DDP_OPT_*).  Valid before ddp_finalize. */
+int ddp_set_option(ddp_problem* p, int option, int64_t value);
+
+/* Validate, pack points and parameters into device memory, build the work
+ * list, and (fused = 1) capture one training step as a HIP graph on
+ * hip_stream (a hipStream_t, or NULL for the null stream).  fused = 0 selects
+ * the per-subdomain path: the same kernels launched once per subdomain,
+ * without the persistent schedule or a graph.  Parameters start at zero;
+ * set them with ddp_set_params.  Topology calls fail with DDP_ESTATE after. */
+int ddp_finalize(ddp_problem* p, void* hip_stream, int fused);
+
+/* Number of parameters of subdomain sd's network (canonical layout). */
+int ddp_param_count(const ddp_problem* p, int sd, int64_t* n);
+
+/* Copy subdomain sd's parameters in (set) or out (get), canonical layout.
+ * Stream-ordered after ddp_finalize. */
+int ddp_set_params(ddp_problem* p, int sd, const float* flat, int on_device);
+int ddp_get_params(ddp_problem* p, int sd, float* flat, int on_device);
+
+/* Evaluate the loss of every subdomain and dJ(Theta_q)/dTheta_q (neighbour
+ * interface values held fixed), without updating parameters.
+ * loss_terms: device, n_sd x 5 = (J, MSE_u, MSE_F, MSE_uavg, MSE_flux|MSE_R).
+ * grad: device, all subdomains' gradients concatenated in subdomain order,
+ * canonical layout (may be NULL).  Stream-ordered. */
+int ddp_loss_and_grad(ddp_problem* p, float* loss_terms, float* grad);
+
+/* Run n_steps training steps (loss, gradient, Adam with beta = (0.9, 0.999),
+ * eps = 1e-8).  loss_terms (device, may be NULL) receives the terms of the
+ * last step, evaluated at the parameters before its update. */
+int ddp_step(ddp_problem* p, int n_steps, float* loss_terms);
+
+/* Adam state: m and v (host, all parameters concatenated) and the number of
+ * completed steps t.  ddp_get_state synchronises the stream. */
+int ddp_get_state(ddp_problem* p, float* m, float* v, int64_t* t);
+int ddp_set_state(ddp_problem* p, const float* m, const float* v, int64_t t);
+
+/* Stitched solution of Eq. FSol at n points (device xy, n x 2).  owner (device,
+ * n x 4 int32, -1 padded) lists the subdomains whose closure holds each point;
+ * the output (device, n x N_L) averages their networks (indicator 1/S). */
+int ddp_eval(ddp_problem* p, int n, const float* xy, const int* owner, float* u_out);
+
+/* Wait for the stream; DDP_ENONFINITE if a loss since the last sync was not
+ * finite (the flag is then cleared). */
+int ddp_sync(ddp_problem* p);
+
+/* Average device time in milliseconds of each kernel of one fused step
+ * (interface values, per-subdomain loss and gradient, reduction and Adam),
+ * measured with HIP events over iters launches of each on the problem's
+ * stream.  ms must hold 3 floats.  Leaves parameters unchanged. */
+int ddp_time_kernels(ddp_problem* p, int iters, float* ms);
+
+/* Write the packed plan (subdomains, interfaces, work items, offsets) as JSON.
+ * Host only; valid after ddp_plan (or ddp_finalize). */
+int ddp_plan_dump(const ddp_problem* p, const char* json_path);
+
+/* Build the packed plan on the host without touching the GPU (what
+ * ddp_finalize does before it allocates); for inspection and tests. */
+int ddp_plan(ddp_problem* p);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* ddp_last_error(void);
+
+/* Release all host and device resources of the handle. */
+int ddp_destroy(ddp_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDPINN_H */

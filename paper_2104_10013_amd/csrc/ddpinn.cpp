@@ -1,0 +1,839 @@
+// libddpinn: host side of the C ABI declared in include/ddpinn.h.
+//
+// Builds the packed plan (per-network descriptors, point arrays, interface
+// table, work items in descending-cost order, gradient partial rows), owns
+// the device buffers, launches the kernels of kernels.hip, and captures the
+// fused step as a HIP graph.
+#include "../../include/ddpinn.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ddp_internal.h"
+#include "kernels.h"
+
+using namespace ddp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(DDP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+struct HostSd {
+  std::vector<int> widths;
+  float loss_w[4];
+  float lr;
+  std::vector<float> res_xy, res_f, dat_xy, dat_g;
+  int n_res = 0, n_dat = 0;
+};
+
+struct HostIf {
+  int a, b, n;
+  std::vector<float> xy;
+  float nx, ny;
+};
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+bool all_finite(const float* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+int width_class(int w) { return ((w + 15) / 16) * 16; }
+
+}  // namespace
+
+struct ddp_problem {
+  int method = 0, pde = 0;
+  double coef[4] = {0, 0, 0, 0};
+  int n_eq = 1, d_out = 1, n_val = 2;
+  std::vector<HostSd> sds;
+  std::vector<HostIf> ifs;
+  int64_t chunk_points = 256;
+  int blocks_per_cu = 0;  // 0: from the occupancy query
+
+  // plan
+  bool planned = false, finalized = false;
+  int fused = 1;
+  int wpmax = 16;
+  std::vector<NetDesc> nets;
+  std::vector<int64_t> sd_poff;  // n_sd + 1
+  std::vector<Item> titems;      // train items (fused: descending cost; plain: grouped by q)
+  std::vector<Item> vitems;      // interface-value items, grouped by q
+  std::vector<int> t_begin, v_begin;  // per q ranges (plain path), n_sd + 1
+  std::vector<IfaceDesc> ifaces;
+  std::vector<int> sd_rows, sd_row_ptr, row_lrow;
+  std::vector<int64_t> row_prow;
+  int64_t partial_floats = 0;
+  std::vector<float> h_res_xy, h_res_f, h_dat_xy, h_dat_g, h_if_xy;
+
+  // device
+  int device = 0;
+  hipStream_t stream = nullptr;      // caller's stream
+  hipStream_t cap_stream = nullptr;  // private stream used for graph capture
+  int n_slots = 0;
+  int64_t slot_floats = 0;
+  float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr;
+  int *d_tstate = nullptr, *d_flags = nullptr, *d_counters = nullptr;
+  int n_counters = 0;
+  NetDesc* d_nets = nullptr;
+  Item *d_titems = nullptr, *d_vitems = nullptr;
+  IfaceDesc* d_ifaces = nullptr;
+  float *d_res_xy = nullptr, *d_res_f = nullptr, *d_dat_xy = nullptr, *d_dat_g = nullptr;
+  float *d_if_xy = nullptr, *d_if_val = nullptr;
+  float *d_partial = nullptr, *d_loss_part = nullptr, *d_scratch = nullptr, *d_loss = nullptr;
+  int64_t* d_sd_poff = nullptr;
+  int *d_sd_rows = nullptr, *d_sd_row_ptr = nullptr, *d_row_lrow = nullptr;
+  int64_t* d_row_prow = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<void*> allocations;
+};
+
+namespace {
+
+template <class T>
+int dev_alloc(ddp_problem* p, T** out, size_t count) {
+  *out = nullptr;
+  if (count == 0) count = 1;
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+  if (e != hipSuccess) return fail(DDP_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  p->allocations.push_back(ptr);
+  *out = static_cast<T*>(ptr);
+  return DDP_OK;
+}
+
+template <class T>
+int dev_upload(ddp_problem* p, T** out, const std::vector<T>& v) {
+  int rc = dev_alloc(p, out, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIP_TRY(hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return DDP_OK;
+}
+
+int copy_in(const float* src, size_t n, int on_device, std::vector<float>& dst) {
+  dst.resize(n);
+  if (n == 0) return DDP_OK;
+  if (!src) return fail(DDP_EINVAL, "null input pointer");
+  if (on_device) {
+    HIP_TRY(hipMemcpy(dst.data(), src, n * sizeof(float), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(dst.data(), src, n * sizeof(float));
+  }
+  return DDP_OK;
+}
+
+int64_t net_param_count(const std::vector<int>& wd) {
+  int64_t n = 0;
+  for (size_t k = 1; k < wd.size(); ++k) n += (int64_t)wd[k] * wd[k - 1] + wd[k];
+  return n;
+}
+
+double item_cost(const NetDesc& nd, int count) {
+  // MFMA work of one item: streams x padded hidden products, forward + backward
+  const double wp = nd.wclass;
+  return (double)count * (1.0 + (nd.depth - 1) * wp * wp * 24.0 + 40.0 * wp);
+}
+
+int build_plan(ddp_problem* p) {
+  const int n_sd = (int)p->sds.size();
+  if (n_sd == 0) return fail(DDP_EINVAL, "no subdomains");
+  for (const HostIf& f : p->ifs)
+    if (f.a >= n_sd || f.b >= n_sd) return fail(DDP_EINVAL, "interface names an unknown subdomain");
+  int64_t chunk = std::max<int64_t>(kTilePts, (p->chunk_points + kTilePts - 1) / kTilePts * kTilePts);
+
+  // networks and parameter offsets
+  p->nets.assign(n_sd, NetDesc{});
+  p->sd_poff.assign(n_sd + 1, 0);
+  p->wpmax = 16;
+  for (int q = 0; q < n_sd; ++q) {
+    const HostSd& s = p->sds[q];
+    NetDesc& nd = p->nets[q];
+    nd.width = s.widths[1];
+    nd.depth = (int)s.widths.size() - 2;
+    nd.d_out = s.widths.back();
+    nd.wclass = width_class(nd.width);
+    nd.poff = p->sd_poff[q];
+    nd.n_params = (int)net_param_count(s.widths);
+    for (int k = 0; k < 4; ++k) nd.loss_w[k] = s.loss_w[k];
+    nd.lr = s.lr;
+    p->sd_poff[q + 1] = p->sd_poff[q] + nd.n_params;
+    p->wpmax = std::max(p->wpmax, nd.wclass);
+  }
+
+  // packed point arrays
+  p->h_res_xy.clear();
+  p->h_res_f.clear();
+  p->h_dat_xy.clear();
+  p->h_dat_g.clear();
+  p->h_if_xy.clear();
+  std::vector<int> res_begin(n_sd), dat_begin(n_sd);
+  for (int q = 0; q < n_sd; ++q) {
+    const HostSd& s = p->sds[q];
+    res_begin[q] = (int)(p->h_res_xy.size() / 2);
+    p->h_res_xy.insert(p->h_res_xy.end(), s.res_xy.begin(), s.res_xy.end());
+    p->h_res_f.insert(p->h_res_f.end(), s.res_f.begin(), s.res_f.end());
+    dat_begin[q] = (int)(p->h_dat_xy.size() / 2);
+    p->h_dat_xy.insert(p->h_dat_xy.end(), s.dat_xy.begin(), s.dat_xy.end());
+    p->h_dat_g.insert(p->h_dat_g.end(), s.dat_g.begin(), s.dat_g.end());
+  }
+  p->ifaces.clear();
+  for (const HostIf& f : p->ifs) {
+    IfaceDesc d;
+    d.a = f.a;
+    d.b = f.b;
+    d.begin = (int)(p->h_if_xy.size() / 2);
+    d.count = f.n;
+    d.nx = f.nx;
+    d.ny = f.ny;
+    p->h_if_xy.insert(p->h_if_xy.end(), f.xy.begin(), f.xy.end());
+    p->ifaces.push_back(d);
+  }
+
+  // work items per subdomain: residual, data and interface-side chunks
+  std::vector<std::vector<Item>> per_q(n_sd), vper_q(n_sd);
+  auto add_chunks = [&](int q, int kind, int begin, int count, int iface, int side, float inv_n) {
+    for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+      Item it{};
+      it.q = q;
+      it.kind = kind;
+      it.begin = begin + (int)c0;
+      it.count = (int)std::min<int64_t>(chunk, count - c0);
+      it.iface = iface;
+      it.side = side;
+      it.inv_n = inv_n;
+      per_q[q].push_back(it);
+      if (kind == KIND_IFACE) vper_q[q].push_back(it);
+    }
+  };
+  for (int q = 0; q < n_sd; ++q) {
+    const HostSd& s = p->sds[q];
+    if (s.n_res > 0) add_chunks(q, KIND_RES, res_begin[q], s.n_res, -1, 0, 1.f / (float)s.n_res);
+    if (s.n_dat > 0) add_chunks(q, KIND_DATA, dat_begin[q], s.n_dat, -1, 0, 1.f / (float)s.n_dat);
+  }
+  for (int e = 0; e < (int)p->ifaces.size(); ++e) {
+    const IfaceDesc& d = p->ifaces[e];
+    if (d.count <= 0) continue;
+    add_chunks(d.a, KIND_IFACE, d.begin, d.count, e, 0, 1.f / (float)d.count);
+    add_chunks(d.b, KIND_IFACE, d.begin, d.count, e, 1, 1.f / (float)d.count);
+  }
+
+  // train items: fused = one list in descending cost (largest first, a
+  // greedy longest-processing-time order for the dynamic queue); plain =
+  // grouped by subdomain so each launch takes one contiguous range
+  p->titems.clear();
+  p->t_begin.assign(n_sd + 1, 0);
+  for (int q = 0; q < n_sd; ++q) {
+    p->t_begin[q] = (int)p->titems.size();
+    std::vector<Item> v = per_q[q];
+    std::stable_sort(v.begin(), v.end(), [&](const Item& x, const Item& y) {
+      return item_cost(p->nets[x.q], x.count) > item_cost(p->nets[y.q], y.count);
+    });
+    p->titems.insert(p->titems.end(), v.begin(), v.end());
+  }
+  p->t_begin[n_sd] = (int)p->titems.size();
+  if (p->fused) {
+    std::stable_sort(p->titems.begin(), p->titems.end(), [&](const Item& x, const Item& y) {
+      return item_cost(p->nets[x.q], x.count) > item_cost(p->nets[y.q], y.count);
+    });
+  }
+  // partial rows and loss rows follow item order
+  int64_t off = 0;
+  for (int i = 0; i < (int)p->titems.size(); ++i) {
+    Item& it = p->titems[i];
+    it.lrow = i;
+    it.prow = off;
+    off += p->nets[it.q].n_params;
+  }
+  p->partial_floats = off;
+  // per subdomain row lists (ascending item index: a fixed summation order)
+  p->sd_row_ptr.assign(n_sd + 1, 0);
+  for (const Item& it : p->titems) p->sd_row_ptr[it.q + 1]++;
+  for (int q = 0; q < n_sd; ++q) p->sd_row_ptr[q + 1] += p->sd_row_ptr[q];
+  p->sd_rows.assign(p->titems.size(), 0);
+  {
+    std::vector<int> fill(p->sd_row_ptr.begin(), p->sd_row_ptr.end() - 1);
+    for (int i = 0; i < (int)p->titems.size(); ++i) p->sd_rows[fill[p->titems[i].q]++] = i;
+  }
+  p->row_prow.resize(p->titems.size());
+  p->row_lrow.resize(p->titems.size());
+  for (size_t i = 0; i < p->titems.size(); ++i) {
+    p->row_prow[i] = p->titems[i].prow;
+    p->row_lrow[i] = p->titems[i].lrow;
+  }
+  // interface-value items grouped by subdomain
+  p->vitems.clear();
+  p->v_begin.assign(n_sd + 1, 0);
+  for (int q = 0; q < n_sd; ++q) {
+    p->v_begin[q] = (int)p->vitems.size();
+    p->vitems.insert(p->vitems.end(), vper_q[q].begin(), vper_q[q].end());
+  }
+  p->v_begin[n_sd] = (int)p->vitems.size();
+  p->planned = true;
+  return DDP_OK;
+}
+
+KArgs make_kargs(ddp_problem* p) {
+  KArgs ka{};
+  ka.params = p->d_params;
+  ka.nets = p->d_nets;
+  ka.ifaces = p->d_ifaces;
+  ka.res_xy = p->d_res_xy;
+  ka.res_f = p->d_res_f;
+  ka.dat_xy = p->d_dat_xy;
+  ka.dat_g = p->d_dat_g;
+  ka.if_xy = p->d_if_xy;
+  ka.if_val = p->d_if_val;
+  ka.partial = p->d_partial;
+  ka.loss_part = p->d_loss_part;
+  ka.scratch = p->d_scratch;
+  ka.scratch_slot = p->slot_floats;
+  ka.counters_all = p->d_counters;
+  ka.n_counters = p->n_counters;
+  ka.tstate = p->d_tstate;
+  ka.method = p->method;
+  ka.n_eq = p->n_eq;
+  ka.n_val = p->n_val;
+  ka.coef0 = (float)p->coef[0];
+  return ka;
+}
+
+RArgs make_rargs(ddp_problem* p) {
+  RArgs ra{};
+  ra.params = p->d_params;
+  ra.adam_m = p->d_m;
+  ra.adam_v = p->d_v;
+  ra.partial = p->d_partial;
+  ra.loss_part = p->d_loss_part;
+  ra.nets = p->d_nets;
+  ra.sd_poff = p->d_sd_poff;
+  ra.sd_rows = p->d_sd_rows;
+  ra.sd_row_ptr = p->d_sd_row_ptr;
+  ra.row_prow = p->d_row_prow;
+  ra.row_lrow = p->d_row_lrow;
+  ra.n_sd = (int)p->sds.size();
+  ra.flags = p->d_flags;
+  ra.tstate = p->d_tstate;
+  return ra;
+}
+
+int reduce_grid(ddp_problem* p, int q0, int q1) {
+  const int64_t n = p->sd_poff[q1] - p->sd_poff[q0];
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+}
+
+// kernel sequence of one step (or one loss_and_grad) on stream st
+int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, float* loss_out) {
+  const int n_sd = (int)p->sds.size();
+  if (p->fused) {
+    KArgs ka = make_kargs(p);
+    ka.items = p->d_vitems;
+    ka.n_items = (int)p->vitems.size();
+    ka.prologue = 1;
+    HIP_TRY(launch_values(p->pde, p->wpmax, ka, st));
+    ka = make_kargs(p);
+    ka.items = p->d_titems;
+    ka.n_items = (int)p->titems.size();
+    ka.counter = p->d_counters;
+    const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
+    HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, st));
+    RArgs ra = make_rargs(p);
+    ra.q_begin = 0;
+    ra.q_end = n_sd;
+    ra.grad_out = grad_out;
+    ra.loss_out = loss_out;
+    ra.do_adam = do_adam;
+    HIP_TRY(launch_reduce(ra, reduce_grid(p, 0, n_sd), st));
+    return DDP_OK;
+  }
+  // plain path: the same kernels, one launch set per subdomain
+  for (int q = 0; q < n_sd; ++q) {
+    KArgs ka = make_kargs(p);
+    ka.items = p->d_vitems + p->v_begin[q];
+    ka.n_items = p->v_begin[q + 1] - p->v_begin[q];
+    ka.prologue = q == 0;
+    if (ka.n_items > 0 || q == 0) HIP_TRY(launch_values(p->pde, p->wpmax, ka, st));
+  }
+  for (int q = 0; q < n_sd; ++q) {
+    KArgs ka = make_kargs(p);
+    ka.items = p->d_titems + p->t_begin[q];
+    ka.n_items = p->t_begin[q + 1] - p->t_begin[q];
+    ka.counter = p->d_counters + 1 + q;
+    if (ka.n_items == 0) continue;
+    const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
+    HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, st));
+  }
+  for (int q = 0; q < n_sd; ++q) {
+    RArgs ra = make_rargs(p);
+    ra.q_begin = q;
+    ra.q_end = q + 1;
+    ra.grad_out = grad_out;
+    ra.loss_out = loss_out;
+    ra.do_adam = do_adam;
+    HIP_TRY(launch_reduce(ra, reduce_grid(p, q, q + 1), st));
+  }
+  return DDP_OK;
+}
+
+void release(ddp_problem* p) {
+  if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  for (void* a : p->allocations) hipFree(a);
+  p->allocations.clear();
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  p->cap_stream = nullptr;
+}
+
+int check_open(const ddp_problem* p) {
+  if (!p) return fail(DDP_EINVAL, "null problem handle");
+  if (p->finalized) return fail(DDP_ESTATE, "topology is fixed after ddp_finalize");
+  return DDP_OK;
+}
+
+int check_final(const ddp_problem* p) {
+  if (!p) return fail(DDP_EINVAL, "null problem handle");
+  if (!p->finalized) return fail(DDP_ESTATE, "call ddp_finalize first");
+  return DDP_OK;
+}
+
+void json_ints(FILE* f, const char* name, const std::vector<int>& v) {
+  std::fprintf(f, "\"%s\": [", name);
+  for (size_t i = 0; i < v.size(); ++i) std::fprintf(f, "%s%d", i ? ", " : "", v[i]);
+  std::fprintf(f, "]");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* ddp_last_error(void) { return g_err.c_str(); }
+
+int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n_coef) {
+  if (!out) return fail(DDP_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (method != DDP_CPINN && method != DDP_XPINN) return fail(DDP_EINVAL, "method must be DDP_CPINN or DDP_XPINN");
+  if (pde < DDP_POISSON2D || pde > DDP_NS2D_STEADY) return fail(DDP_EINVAL, "unknown operator");
+  if (n_coef < 0 || n_coef > 4 || (n_coef > 0 && !coef)) return fail(DDP_EINVAL, "bad coefficient array");
+  if ((pde == DDP_BURGERS1D || pde == DDP_NS2D_STEADY) && n_coef < 1)
+    return fail(DDP_EINVAL, "operator needs coef[0] (nu or Re)");
+  for (int i = 0; i < n_coef; ++i)
+    if (!std::isfinite(coef[i]) || coef[i] <= 0) return fail(DDP_EINVAL, "coefficients must be finite and > 0");
+  if (method == DDP_CPINN && pde == DDP_NS2D_STEADY)
+    return fail(DDP_EINVAL, "cPINN flux terms are not provided for Navier-Stokes; use DDP_XPINN");
+  ddp_problem* p = new (std::nothrow) ddp_problem();
+  if (!p) return fail(DDP_ENOMEM, "out of host memory");
+  p->method = method;
+  p->pde = pde;
+  for (int i = 0; i < n_coef; ++i) p->coef[i] = coef[i];
+  p->d_out = pde == DDP_NS2D_STEADY ? 3 : 1;
+  p->n_eq = pde == DDP_NS2D_STEADY ? 3 : 1;
+  p->n_val = p->d_out + p->n_eq;
+  *out = p;
+  return DDP_OK;
+}
+
+int ddp_add_subdomain(ddp_problem* p, int n_nets, const int* n_layers, const int* widths, const float* loss_w,
+                      float lr, int* sd_id) {
+  if (int rc = check_open(p)) return rc;
+  if (n_nets != 1) return fail(DDP_EINVAL, "exactly one network per subdomain is supported");
+  if (!n_layers || !widths || !loss_w) return fail(DDP_EINVAL, "null argument");
+  const int nl = n_layers[0];
+  if (nl < 3) return fail(DDP_EINVAL, "a network needs input, at least one hidden and an output layer");
+  if (nl - 2 > kMaxDepth) return fail(DDP_EINVAL, "at most 8 hidden layers");
+  if (widths[0] != 2) return fail(DDP_EINVAL, "input width must be 2");
+  if (widths[nl - 1] != p->d_out) return fail(DDP_EINVAL, "output width must equal the operator's outputs");
+  const int w = widths[1];
+  if (w < 1 || w > kMaxWidth) return fail(DDP_EINVAL, "hidden width must be in [1, 112]");
+  for (int k = 1; k < nl - 1; ++k)
+    if (widths[k] != w) return fail(DDP_EINVAL, "hidden layers of one network must have equal widths");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(loss_w[k]) || loss_w[k] < 0) return fail(DDP_EINVAL, "loss weights must be finite and >= 0");
+  if (!std::isfinite(lr) || lr <= 0) return fail(DDP_EINVAL, "learning rate must be finite and > 0");
+  HostSd s;
+  s.widths.assign(widths, widths + nl);
+  for (int k = 0; k < 4; ++k) s.loss_w[k] = loss_w[k];
+  s.lr = lr;
+  p->sds.push_back(std::move(s));
+  if (sd_id) *sd_id = (int)p->sds.size() - 1;
+  p->planned = false;
+  return DDP_OK;
+}
+
+int ddp_set_points(ddp_problem* p, int sd, int kind, int n, const float* xy, const float* val, int on_device) {
+  if (int rc = check_open(p)) return rc;
+  if (sd < 0 || sd >= (int)p->sds.size()) return fail(DDP_EINVAL, "unknown subdomain");
+  if (kind != DDP_RESIDUAL && kind != DDP_DATA) return fail(DDP_EINVAL, "unknown point kind");
+  if (n < 0) return fail(DDP_EINVAL, "negative point count");
+  HostSd& s = p->sds[sd];
+  const int nv = kind == DDP_RESIDUAL ? p->n_eq : p->d_out;
+  std::vector<float> hxy, hval;
+  if (int rc = copy_in(xy, (size_t)n * 2, on_device, hxy)) return rc;
+  if (int rc = copy_in(val, (size_t)n * nv, on_device, hval)) return rc;
+  if (!all_finite(hxy.data(), hxy.size()) || !all_finite(hval.data(), hval.size()))
+    return fail(DDP_EINVAL, "non-finite coordinate or value");
+  if (kind == DDP_RESIDUAL) {
+    s.res_xy.swap(hxy);
+    s.res_f.swap(hval);
+    s.n_res = n;
+  } else {
+    s.dat_xy.swap(hxy);
+    s.dat_g.swap(hval);
+    s.n_dat = n;
+  }
+  p->planned = false;
+  return DDP_OK;
+}
+
+int ddp_add_interface(ddp_problem* p, int sd_a, int sd_b, int n, const float* xy, const float normal[2],
+                      int on_device, int* if_id) {
+  if (int rc = check_open(p)) return rc;
+  const int n_sd = (int)p->sds.size();
+  if (sd_a < 0 || sd_b < 0 || sd_a >= n_sd || sd_b >= n_sd) return fail(DDP_EINVAL, "interface names an unknown subdomain");
+  if (sd_a == sd_b) return fail(DDP_EINVAL, "interface needs two different subdomains");
+  if (n < 0) return fail(DDP_EINVAL, "negative point count");
+  if (!normal || !std::isfinite(normal[0]) || !std::isfinite(normal[1])) return fail(DDP_EINVAL, "bad normal");
+  HostIf f;
+  f.a = sd_a;
+  f.b = sd_b;
+  f.n = n;
+  f.nx = normal[0];
+  f.ny = normal[1];
+  if (int rc = copy_in(xy, (size_t)n * 2, on_device, f.xy)) return rc;
+  if (!all_finite(f.xy.data(), f.xy.size())) return fail(DDP_EINVAL, "non-finite coordinate");
+  p->ifs.push_back(std::move(f));
+  if (if_id) *if_id = (int)p->ifs.size() - 1;
+  p->planned = false;
+  return DDP_OK;
+}
+
+int ddp_set_option(ddp_problem* p, int option, int64_t value) {
+  if (int rc = check_open(p)) return rc;
+  switch (option) {
+    case DDP_OPT_CHUNK_POINTS:
+      if (value < 1 || value > (1 << 24)) return fail(DDP_EINVAL, "chunk points out of range");
+      p->chunk_points = value;
+      break;
+    case DDP_OPT_BLOCKS_PER_CU:
+      if (value < 0 || value > 8) return fail(DDP_EINVAL, "blocks per CU out of range");
+      p->blocks_per_cu = (int)value;
+      break;
+    default:
+      return fail(DDP_EINVAL, "unknown option");
+  }
+  p->planned = false;
+  return DDP_OK;
+}
+
+int ddp_plan(ddp_problem* p) {
+  if (int rc = check_open(p)) return rc;
+  return build_plan(p);
+}
+
+int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
+  if (int rc = check_open(p)) return rc;
+  p->fused = fused ? 1 : 0;
+  if (int rc = build_plan(p)) return rc;
+  const int n_sd = (int)p->sds.size();
+  HIP_TRY(hipGetDevice(&p->device));
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  int n_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
+  int occ = 0;
+  HIP_TRY(train_occupancy(p->pde, p->wpmax, &occ));
+  if (occ < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
+  const int bpc = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, occ) : occ;
+  p->n_slots = std::max(1, n_cu * bpc);
+  p->slot_floats = scratch_slot_floats(p->wpmax);
+  p->n_counters = n_sd + 1;
+
+  int rc = 0;
+  std::vector<float> zeros(p->sd_poff[n_sd], 0.f);
+  if ((rc = dev_upload(p, &p->d_params, zeros))) return rc;
+  if ((rc = dev_upload(p, &p->d_m, zeros))) return rc;
+  if ((rc = dev_upload(p, &p->d_v, zeros))) return rc;
+  if ((rc = dev_upload(p, &p->d_tstate, std::vector<int>{0, 0}))) return rc;
+  if ((rc = dev_upload(p, &p->d_flags, std::vector<int>{0, 0}))) return rc;
+  if ((rc = dev_upload(p, &p->d_counters, std::vector<int>(p->n_counters, 0)))) return rc;
+  if ((rc = dev_upload(p, &p->d_nets, p->nets))) return rc;
+  if ((rc = dev_upload(p, &p->d_titems, p->titems))) return rc;
+  if ((rc = dev_upload(p, &p->d_vitems, p->vitems))) return rc;
+  if ((rc = dev_upload(p, &p->d_ifaces, p->ifaces))) return rc;
+  if ((rc = dev_upload(p, &p->d_res_xy, p->h_res_xy))) return rc;
+  if ((rc = dev_upload(p, &p->d_res_f, p->h_res_f))) return rc;
+  if ((rc = dev_upload(p, &p->d_dat_xy, p->h_dat_xy))) return rc;
+  if ((rc = dev_upload(p, &p->d_dat_g, p->h_dat_g))) return rc;
+  if ((rc = dev_upload(p, &p->d_if_xy, p->h_if_xy))) return rc;
+  if ((rc = dev_upload(p, &p->d_if_val, std::vector<float>(p->h_if_xy.size() / 2 * 2 * p->n_val, 0.f)))) return rc;
+  if ((rc = dev_alloc(p, &p->d_partial, (size_t)p->partial_floats))) return rc;
+  if ((rc = dev_alloc(p, &p->d_loss_part, p->titems.size() * kLossTerms))) return rc;
+  if ((rc = dev_alloc(p, &p->d_scratch, (size_t)p->n_slots * p->slot_floats))) return rc;
+  if ((rc = dev_alloc(p, &p->d_loss, (size_t)n_sd * 5))) return rc;
+  if ((rc = dev_upload(p, &p->d_sd_poff, p->sd_poff))) return rc;
+  if ((rc = dev_upload(p, &p->d_sd_rows, p->sd_rows))) return rc;
+  if ((rc = dev_upload(p, &p->d_sd_row_ptr, p->sd_row_ptr))) return rc;
+  if ((rc = dev_upload(p, &p->d_row_prow, p->row_prow))) return rc;
+  if ((rc = dev_upload(p, &p->d_row_lrow, p->row_lrow))) return rc;
+  HIP_TRY(hipMemset(p->d_partial, 0, (size_t)std::max<int64_t>(1, p->partial_floats) * sizeof(float)));
+  HIP_TRY(hipMemset(p->d_loss_part, 0, std::max<size_t>(1, p->titems.size() * kLossTerms) * sizeof(float)));
+  HIP_TRY(hipDeviceSynchronize());
+
+  if (p->fused) {
+    // one training step as a graph: captured on a private stream, replayed on
+    // the caller's stream
+    HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_step(p, p->cap_stream, 1, nullptr, p->d_loss);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(DDP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    p->graph = g;
+    HIP_TRY(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+  }
+  p->finalized = true;
+  return DDP_OK;
+}
+
+int ddp_param_count(const ddp_problem* p, int sd, int64_t* n) {
+  if (!p || !n) return fail(DDP_EINVAL, "null argument");
+  if (sd < 0 || sd >= (int)p->sds.size()) return fail(DDP_EINVAL, "unknown subdomain");
+  *n = net_param_count(p->sds[sd].widths);
+  return DDP_OK;
+}
+
+int ddp_set_params(ddp_problem* p, int sd, const float* flat, int on_device) {
+  if (int rc = check_final(p)) return rc;
+  if (sd < 0 || sd >= (int)p->sds.size() || !flat) return fail(DDP_EINVAL, "bad subdomain or null pointer");
+  const size_t n = (size_t)p->nets[sd].n_params;
+  HIP_TRY(hipMemcpyAsync(p->d_params + p->sd_poff[sd], flat, n * sizeof(float),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(p->stream));
+  return DDP_OK;
+}
+
+int ddp_get_params(ddp_problem* p, int sd, float* flat, int on_device) {
+  if (int rc = check_final(p)) return rc;
+  if (sd < 0 || sd >= (int)p->sds.size() || !flat) return fail(DDP_EINVAL, "bad subdomain or null pointer");
+  const size_t n = (size_t)p->nets[sd].n_params;
+  HIP_TRY(hipMemcpyAsync(flat, p->d_params + p->sd_poff[sd], n * sizeof(float),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(p->stream));
+  return DDP_OK;
+}
+
+int ddp_loss_and_grad(ddp_problem* p, float* loss_terms, float* grad) {
+  if (int rc = check_final(p)) return rc;
+  return enqueue_step(p, p->stream, 0, grad, loss_terms ? loss_terms : p->d_loss);
+}
+
+int ddp_step(ddp_problem* p, int n_steps, float* loss_terms) {
+  if (int rc = check_final(p)) return rc;
+  if (n_steps < 0) return fail(DDP_EINVAL, "negative step count");
+  for (int s = 0; s < n_steps; ++s) {
+    if (p->fused) {
+      HIP_TRY(hipGraphLaunch(p->graph_exec, p->stream));
+    } else {
+      if (int rc = enqueue_step(p, p->stream, 1, nullptr, p->d_loss)) return rc;
+    }
+  }
+  if (loss_terms && n_steps > 0)
+    HIP_TRY(hipMemcpyAsync(loss_terms, p->d_loss, p->sds.size() * 5 * sizeof(float), hipMemcpyDeviceToDevice,
+                           p->stream));
+  return DDP_OK;
+}
+
+int ddp_get_state(ddp_problem* p, float* m, float* v, int64_t* t) {
+  if (int rc = check_final(p)) return rc;
+  const size_t n = (size_t)p->sd_poff.back();
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (m) HIP_TRY(hipMemcpy(m, p->d_m, n * sizeof(float), hipMemcpyDeviceToHost));
+  if (v) HIP_TRY(hipMemcpy(v, p->d_v, n * sizeof(float), hipMemcpyDeviceToHost));
+  if (t) {
+    int ts[2];
+    HIP_TRY(hipMemcpy(ts, p->d_tstate, sizeof(ts), hipMemcpyDeviceToHost));
+    *t = (int64_t)ts[0] + ts[1];
+  }
+  return DDP_OK;
+}
+
+int ddp_set_state(ddp_problem* p, const float* m, const float* v, int64_t t) {
+  if (int rc = check_final(p)) return rc;
+  if (t < 0 || t > (1 << 30)) return fail(DDP_EINVAL, "step count out of range");
+  const size_t n = (size_t)p->sd_poff.back();
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (m) HIP_TRY(hipMemcpy(p->d_m, m, n * sizeof(float), hipMemcpyHostToDevice));
+  if (v) HIP_TRY(hipMemcpy(p->d_v, v, n * sizeof(float), hipMemcpyHostToDevice));
+  int ts[2] = {(int)t, 0};
+  HIP_TRY(hipMemcpy(p->d_tstate, ts, sizeof(ts), hipMemcpyHostToDevice));
+  return DDP_OK;
+}
+
+int ddp_eval(ddp_problem* p, int n, const float* xy, const int* owner, float* u_out) {
+  if (int rc = check_final(p)) return rc;
+  if (n < 0 || (n > 0 && (!xy || !owner || !u_out))) return fail(DDP_EINVAL, "bad evaluation arguments");
+  HIP_TRY(launch_eval(p->d_params, p->d_nets, (int)p->sds.size(), n, xy, owner, u_out, p->d_out, p->stream));
+  return DDP_OK;
+}
+
+int ddp_sync(ddp_problem* p) {
+  if (int rc = check_final(p)) return rc;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  int flags[2];
+  HIP_TRY(hipMemcpy(flags, p->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+  if (flags[0]) {
+    int zero[2] = {0, 0};
+    HIP_TRY(hipMemcpy(p->d_flags, zero, sizeof(zero), hipMemcpyHostToDevice));
+    return fail(DDP_ENONFINITE, "a loss was NaN or inf");
+  }
+  return DDP_OK;
+}
+
+int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
+  if (int rc = check_final(p)) return rc;
+  if (iters < 1 || !ms) return fail(DDP_EINVAL, "bad timing arguments");
+  const int n_sd = (int)p->sds.size();
+  hipEvent_t ev[2];
+  HIP_TRY(hipEventCreate(&ev[0]));
+  HIP_TRY(hipEventCreate(&ev[1]));
+  for (int which = 0; which < 3; ++which) {
+    float total = 0.f;
+    for (int i = 0; i < iters; ++i) {
+      if (which == 1) {
+        // clear the work counters outside the timed window
+        KArgs kz = make_kargs(p);
+        kz.items = p->d_vitems;
+        kz.n_items = 0;
+        kz.prologue = 1;
+        HIP_TRY(launch_values(p->pde, p->wpmax, kz, p->stream));
+      }
+      HIP_TRY(hipEventRecord(ev[0], p->stream));
+      if (which == 0) {
+        KArgs ka = make_kargs(p);
+        ka.items = p->d_vitems;
+        ka.n_items = (int)p->vitems.size();
+        ka.prologue = 1;
+        HIP_TRY(launch_values(p->pde, p->wpmax, ka, p->stream));
+      } else if (which == 1) {
+        if (p->fused) {
+          KArgs ka = make_kargs(p);
+          ka.items = p->d_titems;
+          ka.n_items = (int)p->titems.size();
+          ka.counter = p->d_counters;
+          const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
+          HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, p->stream));
+        } else {
+          for (int q = 0; q < n_sd; ++q) {
+            KArgs ka = make_kargs(p);
+            ka.items = p->d_titems + p->t_begin[q];
+            ka.n_items = p->t_begin[q + 1] - p->t_begin[q];
+            ka.counter = p->d_counters + 1 + q;
+            if (ka.n_items == 0) continue;
+            const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
+            HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, p->stream));
+          }
+        }
+      } else {
+        RArgs ra = make_rargs(p);
+        ra.q_begin = 0;
+        ra.q_end = n_sd;
+        ra.loss_out = p->d_loss;
+        ra.do_adam = 0;
+        HIP_TRY(launch_reduce(ra, reduce_grid(p, 0, n_sd), p->stream));
+      }
+      HIP_TRY(hipEventRecord(ev[1], p->stream));
+      HIP_TRY(hipEventSynchronize(ev[1]));
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, ev[0], ev[1]));
+      total += t;
+    }
+    ms[which] = total / iters;
+  }
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  return DDP_OK;
+}
+
+int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
+  if (!p || !json_path) return fail(DDP_EINVAL, "null argument");
+  if (!p->planned) return fail(DDP_ESTATE, "no plan: call ddp_plan or ddp_finalize first");
+  FILE* f = std::fopen(json_path, "w");
+  if (!f) return fail(DDP_EINVAL, std::string("cannot open ") + json_path);
+  std::fprintf(f, "{\"method\": %d, \"pde\": %d, \"fused\": %d, \"wpmax\": %d, \"tile_points\": %d,\n", p->method,
+               p->pde, p->fused, p->wpmax, kTilePts);
+  std::fprintf(f, "\"nets\": [");
+  for (size_t q = 0; q < p->nets.size(); ++q) {
+    const NetDesc& n = p->nets[q];
+    std::fprintf(f, "%s{\"width\": %d, \"depth\": %d, \"d_out\": %d, \"wclass\": %d, \"poff\": %lld, \"n_params\": %d}",
+                 q ? ", " : "", n.width, n.depth, n.d_out, n.wclass, (long long)n.poff, n.n_params);
+  }
+  std::fprintf(f, "],\n\"ifaces\": [");
+  for (size_t e = 0; e < p->ifaces.size(); ++e) {
+    const IfaceDesc& d = p->ifaces[e];
+    std::fprintf(f, "%s{\"a\": %d, \"b\": %d, \"begin\": %d, \"count\": %d}", e ? ", " : "", d.a, d.b, d.begin,
+                 d.count);
+  }
+  auto items = [&](const char* name, const std::vector<Item>& v) {
+    std::fprintf(f, "],\n\"%s\": [", name);
+    for (size_t i = 0; i < v.size(); ++i) {
+      const Item& it = v[i];
+      std::fprintf(f, "%s[%d, %d, %d, %d, %d, %d, %d, %lld]", i ? ", " : "", it.q, it.kind, it.begin, it.count, it.iface,
+                   it.side, it.lrow, (long long)it.prow);
+    }
+  };
+  items("train_items", p->titems);
+  items("value_items", p->vitems);
+  std::fprintf(f, "],\n");
+  json_ints(f, "sd_row_ptr", p->sd_row_ptr);
+  std::fprintf(f, ",\n");
+  json_ints(f, "sd_rows", p->sd_rows);
+  std::fprintf(f, ",\n");
+  json_ints(f, "t_begin", p->t_begin);
+  std::fprintf(f, ",\n\"partial_floats\": %lld, \"n_res\": %zu, \"n_dat\": %zu, \"n_if\": %zu}\n",
+               (long long)p->partial_floats, p->h_res_xy.size() / 2, p->h_dat_xy.size() / 2, p->h_if_xy.size() / 2);
+  std::fclose(f);
+  return DDP_OK;
+}
+
+int ddp_destroy(ddp_problem* p) {
+  if (!p) return fail(DDP_EINVAL, "null problem handle");
+  if (p->finalized) hipStreamSynchronize(p->stream);
+  release(p);
+  delete p;
+  return DDP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,26 @@
+// Host-side entry points of the gfx950 kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "ddp_internal.h"
+
+namespace ddp {
+
+// dynamic LDS bytes of the values (train = false) or train kernel for a width class
+size_t lds_bytes(int pde, int wpmax, bool train);
+// floats of one workgroup's activation stash for the widest class wpmax
+int64_t scratch_slot_floats(int wpmax);
+// resident train workgroups per compute unit (also raises the LDS limit)
+hipError_t train_occupancy(int pde, int wpmax, int* blocks_per_cu);
+
+// interface values: one workgroup per item; ka.prologue settles Adam's t and
+// clears the work counters
+hipError_t launch_values(int pde, int wpmax, const KArgs& ka, hipStream_t st);
+// persistent loss + gradient-partial kernel over ka.items
+hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream_t st);
+// gradient reduction, loss reduction and optional Adam
+hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st);
+// stitched evaluation
+hipError_t launch_eval(const float* params, const NetDesc* nets, int n_sd, int n, const float* xy, const int* owner,
+                       float* out, int d_out, hipStream_t st);
+
+}  // namespace ddp

@@ -1,0 +1,1012 @@
+// gfx950 kernels of one cPINN / XPINN training step.
+//
+// Each workgroup (4 waves) evaluates one network on a tile of 64 points,
+// 16 points per wave.  The network value and its input derivatives are carried
+// forward as four "streams" per (neuron, point): value, d/dz0, d/dz1 and the
+// second-order sum over the set S the operator needs (S = {x, y} for the
+// Laplacian, S = {x} for Burgers' u_xx).  For a hidden layer
+//     a = W h + b,  a_i = W h_i,  a_S = W h_S          (Sec. 3 recurrence)
+// and through tanh, with t = tanh a, s1 = sech^2 a, s2 = -2 t s1:
+//     h = t,  h_i = s1 a_i,  h_S = s1 a_S + s2 sum_{i in S} a_i^2.
+// The four streams of 16 points are the columns of one FP32 MFMA contraction
+// per layer (v_mfma_f32_16x16x4_f32, weights from LDS); the output layout of
+// one layer is the B operand of the next with the K index permuted, so the
+// tanh rule stays lane-local.  Pre-activation streams are stashed per
+// workgroup in global memory for the reverse pass.
+//
+// The reverse (adjoint) pass differentiates the subdomain loss of
+// Eq. cPINNLoss / Eq. XPINNLoss with respect to the subdomain's own
+// parameters: seeds at the output from the PDE residual, data and interface
+// terms, the adjoint of the tanh rule (s3 = -2 s1 (1 - 3 t^2))
+//     abar_S = s1 g_S
+//     abar_i = s1 g_i + 2 s2 a_i g_S            (i in S; s1 g_i otherwise)
+//     abar   = s1 g + s2 sum_i a_i g_i + (s2 a_S + s3 sum_{i in S} a_i^2) g_S
+// then g_prev = W^T abar (MFMA) and dW = sum over points and streams of
+// abar h_prev^T (MFMA over LDS-staged tiles).  Every work item writes its own
+// gradient partial row; a second kernel sums the rows of each subdomain in a
+// fixed order (deterministic, no float atomics) and applies Adam.
+
+#include <hip/hip_runtime.h>
+#include "ddp_internal.h"
+#include "kernels.h"
+
+namespace ddp {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int TP = kTilePts;      // points per tile
+constexpr int TPS = kTilePts + 4; // LDS row stride of staged tiles (floats)
+constexpr int NT = 64 * kWaves;   // threads per workgroup
+
+__device__ __forceinline__ f4 mma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// tanh(a) and sech^2(a) from e = exp(-2|a|):  t = sign(a)(1-e)/(1+e),
+// s1 = 4e/(1+e)^2 (no cancellation for large |a|).
+__device__ __forceinline__ void tanh_s1(float a, float& t, float& s1) {
+  const float e = __expf(-2.f * fabsf(a));
+  const float r = __builtin_amdgcn_rcpf(1.f + e);
+  t = copysignf((1.f - e) * r, a);
+  s1 = 4.f * e * r * r;
+}
+
+// Sums over the TP points of LDS-staged rows (16-byte aligned), partially unrolled.
+__device__ __forceinline__ float row_sum(const float* a) {
+  float acc = 0.f;
+#pragma unroll 2
+  for (int p = 0; p < TP; p += 4) {
+    const f4 x = *reinterpret_cast<const f4*>(a + p);
+    acc += (x[0] + x[1]) + (x[2] + x[3]);
+  }
+  return acc;
+}
+__device__ __forceinline__ float row_dot(const float* a, const float* b, float acc) {
+#pragma unroll 2
+  for (int p = 0; p < TP; p += 4) {
+    const f4 x = *reinterpret_cast<const f4*>(a + p);
+    const f4 y = *reinterpret_cast<const f4*>(b + p);
+    acc = fmaf(x[0], y[0], fmaf(x[1], y[1], fmaf(x[2], y[2], fmaf(x[3], y[3], acc))));
+  }
+  return acc;
+}
+// sum_p (a[p] * z[p] + h[p])
+__device__ __forceinline__ float row_dot_plus(const float* a, const float* z, const float* h) {
+  float acc = 0.f;
+#pragma unroll 2
+  for (int p = 0; p < TP; p += 4) {
+    const f4 x = *reinterpret_cast<const f4*>(a + p);
+    const f4 y = *reinterpret_cast<const f4*>(z + p);
+    const f4 c = *reinterpret_cast<const f4*>(h + p);
+    acc += fmaf(x[0], y[0], c[0]) + fmaf(x[1], y[1], c[1]) + fmaf(x[2], y[2], c[2]) + fmaf(x[3], y[3], c[3]);
+  }
+  return acc;
+}
+
+template <bool S2>
+__device__ __forceinline__ void tanh_rule(float a, float ax, float ay, float al, float& h, float& hx,
+                                          float& hy, float& hl) {
+  float t, s1;
+  tanh_s1(a, t, s1);
+  const float s2 = -2.f * t * s1;
+  h = t;
+  hx = s1 * ax;
+  hy = s1 * ay;
+  const float q = S2 ? fmaf(ax, ax, ay * ay) : ax * ax;
+  hl = fmaf(s1, al, s2 * q);
+}
+
+template <bool S2>
+__device__ __forceinline__ void tanh_adj(float a, float ax, float ay, float al, float g, float gx,
+                                         float gy, float gl, float& ab, float& abx, float& aby,
+                                         float& abl) {
+  float t, s1;
+  tanh_s1(a, t, s1);
+  const float s2 = -2.f * t * s1;
+  const float s3 = -2.f * s1 * (1.f - 3.f * t * t);
+  const float q = S2 ? fmaf(ax, ax, ay * ay) : ax * ax;
+  abl = s1 * gl;
+  abx = fmaf(s1, gx, 2.f * s2 * ax * gl);
+  aby = S2 ? fmaf(s1, gy, 2.f * s2 * ay * gl) : s1 * gy;
+  ab = fmaf(s1, g, fmaf(s2, fmaf(ax, gx, ay * gy), fmaf(s2, al, s3 * q) * gl));
+}
+
+// ---------------------------------------------------------------------------
+// Operators.  u[c][s]: output c, stream s = (value, d/dz0, d/dz1, second order).
+
+template <int PDE> struct Op;
+
+// -Lap u = f   (F = -u_S - f; flux f = -grad u)
+template <> struct Op<PDE_POISSON> {
+  static constexpr int DO = 1, NEQ = 1;
+  static constexpr bool S2 = true;
+  __device__ static void residual(const float (&u)[DO][4], const float* f, float coef, float (&F)[NEQ]) {
+    F[0] = -u[0][3] - f[0];
+  }
+  __device__ static void residual_adj(const float (&u)[DO][4], const float (&c)[NEQ], float coef,
+                                      float (&ub)[DO][4]) {
+    ub[0][3] -= c[0];
+  }
+  __device__ static float flux(const float (&u)[DO][4], float nx, float ny, float coef) {
+    return -(nx * u[0][1] + ny * u[0][2]);
+  }
+  __device__ static void flux_adj(const float (&u)[DO][4], float nx, float ny, float coef, float c,
+                                  float (&ub)[DO][4]) {
+    ub[0][1] -= c * nx;
+    ub[0][2] -= c * ny;
+  }
+};
+
+// u_t + u u_x - nu u_xx = f, inputs (x, t); space-time flux (u^2/2 - nu u_x, u)
+template <> struct Op<PDE_BURGERS> {
+  static constexpr int DO = 1, NEQ = 1;
+  static constexpr bool S2 = false;
+  __device__ static void residual(const float (&u)[DO][4], const float* f, float nu, float (&F)[NEQ]) {
+    F[0] = u[0][2] + u[0][0] * u[0][1] - nu * u[0][3] - f[0];
+  }
+  __device__ static void residual_adj(const float (&u)[DO][4], const float (&c)[NEQ], float nu,
+                                      float (&ub)[DO][4]) {
+    ub[0][2] += c[0];
+    ub[0][0] += c[0] * u[0][1];
+    ub[0][1] += c[0] * u[0][0];
+    ub[0][3] -= nu * c[0];
+  }
+  __device__ static float flux(const float (&u)[DO][4], float nx, float ny, float nu) {
+    return nx * (0.5f * u[0][0] * u[0][0] - nu * u[0][1]) + ny * u[0][0];
+  }
+  __device__ static void flux_adj(const float (&u)[DO][4], float nx, float ny, float nu, float c,
+                                  float (&ub)[DO][4]) {
+    ub[0][0] += c * (nx * u[0][0] + ny);
+    ub[0][1] -= c * nx * nu;
+  }
+};
+
+// steady incompressible Navier-Stokes, outputs (u, v, p), coef = Re
+template <> struct Op<PDE_NS> {
+  static constexpr int DO = 3, NEQ = 3;
+  static constexpr bool S2 = true;
+  __device__ static void residual(const float (&u)[DO][4], const float* f, float re, float (&F)[NEQ]) {
+    const float ir = 1.f / re;
+    F[0] = u[0][0] * u[0][1] + u[1][0] * u[0][2] + u[2][1] - ir * u[0][3] - f[0];
+    F[1] = u[0][0] * u[1][1] + u[1][0] * u[1][2] + u[2][2] - ir * u[1][3] - f[1];
+    F[2] = u[0][1] + u[1][2] - f[2];
+  }
+  __device__ static void residual_adj(const float (&u)[DO][4], const float (&c)[NEQ], float re,
+                                      float (&ub)[DO][4]) {
+    const float ir = 1.f / re;
+    ub[0][0] += c[0] * u[0][1] + c[1] * u[1][1];
+    ub[0][1] += c[0] * u[0][0] + c[2];
+    ub[0][2] += c[0] * u[1][0];
+    ub[0][3] -= c[0] * ir;
+    ub[1][0] += c[0] * u[0][2] + c[1] * u[1][2];
+    ub[1][1] += c[1] * u[0][0];
+    ub[1][2] += c[1] * u[1][0] + c[2];
+    ub[1][3] -= c[1] * ir;
+    ub[2][1] += c[0];
+    ub[2][2] += c[1];
+  }
+  __device__ static float flux(const float (&u)[DO][4], float nx, float ny, float coef) { return 0.f; }
+  __device__ static void flux_adj(const float (&u)[DO][4], float, float, float, float, float (&)[DO][4]) {}
+};
+
+// ---------------------------------------------------------------------------
+// Tile processor for one padded width class WP.
+
+template <int WP, int PDE>
+struct Tile {
+  static constexpr int MB = WP / 16;
+  static constexpr int DO = Op<PDE>::DO;
+  static constexpr int NEQ = Op<PDE>::NEQ;
+  static constexpr bool S2 = Op<PDE>::S2;
+  static constexpr int WS = WP + 4;                         // LDS row stride of weights
+  static constexpr int NB = (MB * MB + kWaves - 1) / kWaves; // dW blocks per wave
+  static constexpr int KL = (DO * WP + NT - 1) / NT;         // output-layer slots per thread
+
+  typedef f4 Streams[4][MB];
+
+  // layer 1: a = W^1 z + b^1, a_0 = W^1[:,0], a_1 = W^1[:,1], a_S = 0
+  __device__ static void layer1(const float* P, int w, float x, float y, int g, Streams& A) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = 16 * mb + 4 * g + i;
+        float w0 = 0.f, w1 = 0.f, b = 0.f;
+        if (m < w) {
+          w0 = P[2 * m];
+          w1 = P[2 * m + 1];
+          b = P[2 * w + m];
+        }
+        A[0][mb][i] = fmaf(w0, x, fmaf(w1, y, b));
+        A[1][mb][i] = w0;
+        A[2][mb][i] = w1;
+        A[3][mb][i] = 0.f;
+      }
+    }
+  }
+
+  __device__ static void activate(const Streams& A, Streams& H) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float h, hx, hy, hl;
+        tanh_rule<S2>(A[0][mb][i], A[1][mb][i], A[2][mb][i], A[3][mb][i], h, hx, hy, hl);
+        H[0][mb][i] = h;
+        H[1][mb][i] = hx;
+        H[2][mb][i] = hy;
+        H[3][mb][i] = hl;
+      }
+    }
+  }
+
+  // one stream of the activation (used when staging h^{k-1} for dW)
+  __device__ static void activate_stream(const Streams& A, int s, f4 (&Hs)[MB]) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float h, hx, hy, hl;
+        tanh_rule<S2>(A[0][mb][i], A[1][mb][i], A[2][mb][i], A[3][mb][i], h, hx, hy, hl);
+        Hs[mb][i] = s == 0 ? h : (s == 1 ? hx : (s == 2 ? hy : hl));
+      }
+    }
+  }
+
+  // W^k (w x w, row-major in global) -> LDS [m][j], zero padded to WP x WP
+  __device__ static void stage_w(float* sW, const float* Wg, int w) {
+    for (int idx = threadIdx.x; idx < WP * WP; idx += NT) {
+      const int m = idx / WP, j = idx - (idx / WP) * WP;
+      sW[m * WS + j] = (m < w && j < w) ? Wg[m * w + j] : 0.f;
+    }
+  }
+  // W^k transposed -> LDS [j][m]
+  __device__ static void stage_wt(float* sW, const float* Wg, int w) {
+    for (int idx = threadIdx.x; idx < WP * WP; idx += NT) {
+      const int m = idx / WP, j = idx - (idx / WP) * WP;
+      sW[j * WS + m] = (m < w && j < w) ? Wg[m * w + j] : 0.f;
+    }
+  }
+
+  // a^k = W^k h^{k-1} (+ b^k on the value stream), all four streams
+  __device__ static void hidden_fwd(const float* sW, const float* bias, int w, int g, int pc,
+                                    const Streams& H, Streams& A) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = 16 * mb + 4 * g + i;
+        A[0][mb][i] = m < w ? bias[m] : 0.f;
+      }
+      A[1][mb] = f4{0.f, 0.f, 0.f, 0.f};
+      A[2][mb] = f4{0.f, 0.f, 0.f, 0.f};
+      A[3][mb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int kb = 0; kb < MB; ++kb) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const f4 wv = *reinterpret_cast<const f4*>(&sW[(16 * mb + pc) * WS + 16 * kb + 4 * g]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) A[s][mb] = mma(wv[i], H[s][kb][i], A[s][mb]);
+        }
+      }
+    }
+  }
+
+  // g^{k-1}_s = W^{kT} abar^k_s for one stream s (sW holds W^T)
+  __device__ static void hidden_bwd_stream(const float* sWT, int g, int pc, const f4 (&Ab)[MB], f4 (&Gs)[MB]) {
+#pragma unroll
+    for (int jb = 0; jb < MB; ++jb) Gs[jb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int jb = 0; jb < MB; ++jb) {
+        const f4 wv = *reinterpret_cast<const f4*>(&sWT[(16 * jb + pc) * WS + 16 * mb + 4 * g]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Gs[jb] = mma(wv[i], Ab[mb][i], Gs[jb]);
+      }
+    }
+  }
+
+  // stash layout per workgroup slot: [layer k-2][wave][stream][mblock][lane] (float4)
+  __device__ static f4* stash_base(float* slot, int k, int wave, int lane) {
+    return reinterpret_cast<f4*>(slot) + (int64_t)(((k - 2) * kWaves + wave) * 4 * MB) * 64 + lane;
+  }
+
+  // output layer u = W^L h + b^L for DO outputs; every lane group ends with
+  // the full sums for its point (bitwise identical across groups)
+  __device__ static void out_fwd(const float* WL, const float* bL, int w, int g, const Streams& H,
+                                 float (&u)[DO][4]) {
+#pragma unroll
+    for (int c = 0; c < DO; ++c) {
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = 16 * mb + 4 * g + i;
+          const float wv = j < w ? WL[c * w + j] : 0.f;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc[s] = fmaf(wv, H[s][mb][i], acc[s]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        float v = acc[s];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        u[c][s] = s == 0 ? v + bL[c] : v;
+      }
+    }
+  }
+
+  // values this network contributes on an interface: u (DO) then the normal
+  // flux (cPINN) or the operator value L_x(u) without forcing (XPINN)
+  __device__ static void own_values(int method, const float (&u)[DO][4], float nx, float ny, float coef,
+                                    float (&ov)[DO + NEQ]) {
+#pragma unroll
+    for (int c = 0; c < DO; ++c) ov[c] = u[c][0];
+    if (method == METHOD_XPINN) {
+      const float zero[NEQ] = {};
+      float F[NEQ];
+      Op<PDE>::residual(u, zero, coef, F);
+#pragma unroll
+      for (int e = 0; e < NEQ; ++e) ov[DO + e] = F[e];
+    } else {
+      ov[DO] = Op<PDE>::flux(u, nx, ny, coef);
+#pragma unroll
+      for (int e = 1; e < NEQ; ++e) ov[DO + e] = 0.f;
+    }
+  }
+
+  // loss contributions and output seeds of one point (the derivative of the
+  // item's share of J_q with respect to the output streams)
+  __device__ static void epilogue(const KArgs& ka, const Item& it, const NetDesc& nd, int pt, bool valid,
+                                  const float (&u)[DO][4], float (&ub)[DO][4], float (&loss)[kLossTerms]) {
+#pragma unroll
+    for (int c = 0; c < DO; ++c)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ub[c][s] = 0.f;
+#pragma unroll
+    for (int t = 0; t < kLossTerms; ++t) loss[t] = 0.f;
+    if (!valid) return;
+    const float inv_n = it.inv_n;
+    const int gp = it.begin + pt;
+    if (it.kind == KIND_RES) {
+      float F[NEQ];
+      Op<PDE>::residual(u, ka.res_f + (int64_t)gp * ka.n_eq, ka.coef0, F);
+      float c[NEQ];
+#pragma unroll
+      for (int e = 0; e < NEQ; ++e) {
+        loss[1] += F[e] * F[e];
+        c[e] = 2.f * nd.loss_w[1] * F[e] * inv_n;
+      }
+      Op<PDE>::residual_adj(u, c, ka.coef0, ub);
+    } else if (it.kind == KIND_DATA) {
+#pragma unroll
+      for (int c = 0; c < DO; ++c) {
+        const float d = u[c][0] - ka.dat_g[(int64_t)gp * DO + c];
+        loss[0] += d * d;
+        ub[c][0] += 2.f * nd.loss_w[0] * d * inv_n;
+      }
+    } else {
+      const IfaceDesc ifd = ka.ifaces[it.iface];
+      float ov[DO + NEQ];
+      own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
+      const float* nb = ka.if_val + ((int64_t)gp * 2 + (1 - it.side)) * ka.n_val;
+#pragma unroll
+      for (int c = 0; c < DO; ++c) {
+        const float d = ov[c] - nb[c];
+        loss[2] += 0.25f * d * d;
+        ub[c][0] += 0.5f * nd.loss_w[2] * d * inv_n;
+      }
+      if (ka.method == METHOD_XPINN) {
+        float c[NEQ];
+#pragma unroll
+        for (int e = 0; e < NEQ; ++e) {
+          const float d = ov[DO + e] - nb[DO + e];
+          loss[3] += d * d;
+          c[e] = 2.f * nd.loss_w[3] * d * inv_n;
+        }
+        Op<PDE>::residual_adj(u, c, ka.coef0, ub);
+      } else {
+        const float d = ov[DO] - nb[DO];
+        loss[3] += d * d;
+        Op<PDE>::flux_adj(u, ifd.nx, ifd.ny, ka.coef0, 2.f * nd.loss_w[3] * d * inv_n, ub);
+      }
+    }
+  }
+
+  // ------------------------------------------------------------------------
+  // forward only: interface values of this network (first kernel of a step)
+  __device__ static void run_values(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds) {
+    float* sW = lds;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, pc = lane & 15;
+    const int w = nd.width, D = nd.depth;
+    const float* P = ka.params + nd.poff;
+    const IfaceDesc ifd = ka.ifaces[it.iface];
+    for (int t0 = 0; t0 < it.count; t0 += TP) {
+      const int pt = t0 + wave * 16 + pc;
+      const bool valid = pt < it.count;
+      const int gp = it.begin + pt;
+      const float x = valid ? ka.if_xy[2 * (int64_t)gp] : 0.f;
+      const float y = valid ? ka.if_xy[2 * (int64_t)gp + 1] : 0.f;
+      Streams A, H;
+      layer1(P, w, x, y, g, A);
+      activate(A, H);
+      for (int k = 2; k <= D; ++k) {
+        const int64_t off = 3 * w + (int64_t)(k - 2) * (w * w + w);
+        __syncthreads();
+        stage_w(sW, P + off, w);
+        __syncthreads();
+        hidden_fwd(sW, P + off + w * w, w, g, pc, H, A);
+        activate(A, H);
+      }
+      const int64_t offL = 3 * w + (int64_t)(D - 1) * (w * w + w);
+      float u[DO][4];
+      out_fwd(P + offL, P + offL + DO * w, w, g, H, u);
+      if (valid && g == 0) {
+        float ov[DO + NEQ];
+        own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
+        float* dst = ka.if_val + ((int64_t)gp * 2 + it.side) * ka.n_val;
+        for (int v = 0; v < ka.n_val; ++v) dst[v] = ov[v];
+      }
+    }
+  }
+
+  // ------------------------------------------------------------------------
+  // forward, loss, adjoint and parameter-gradient partials of one item
+  __device__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
+                                   float* slot) {
+    float* sW = lds;
+    float* sA = sW + WP * WS;
+    float* sH = sA + WP * TPS;
+    float* sU = sH + WP * TPS;       // [4 streams][3 outputs][TP]
+    float* sX = sU + 4 * 3 * TP;     // [2][TP]
+    float* sRed = sX + 2 * TP;       // [kWaves][kLossTerms]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, pc = lane & 15;
+    const int tp = wave * 16 + pc;
+    const int w = nd.width, D = nd.depth;
+    const float* P = ka.params + nd.poff;
+    float* R = ka.partial + it.prow;
+    const float* xy = it.kind == KIND_RES ? ka.res_xy : (it.kind == KIND_DATA ? ka.dat_xy : ka.if_xy);
+    const int64_t offL = 3 * w + (int64_t)(D - 1) * (w * w + w);
+
+    for (int t0 = 0; t0 < it.count; t0 += TP) {
+      const bool first = t0 == 0;
+      const int pt = t0 + tp;
+      const bool valid = pt < it.count;
+      const int gp = it.begin + pt;
+      const float x = valid ? xy[2 * (int64_t)gp] : 0.f;
+      const float y = valid ? xy[2 * (int64_t)gp + 1] : 0.f;
+      __syncthreads();  // previous tile done with LDS
+      if (g == 0) {
+        sX[tp] = x;
+        sX[TP + tp] = y;
+      }
+
+      // ---- forward: Taylor streams through every layer, stash a^k
+      Streams A, H;
+      layer1(P, w, x, y, g, A);
+      activate(A, H);
+      for (int k = 2; k <= D; ++k) {
+        const int64_t off = 3 * w + (int64_t)(k - 2) * (w * w + w);
+        __syncthreads();
+        stage_w(sW, P + off, w);
+        __syncthreads();
+        hidden_fwd(sW, P + off + w * w, w, g, pc, H, A);
+        {
+          f4* sb = stash_base(slot, k, wave, lane);
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) sb[(s * MB + mb) * 64] = A[s][mb];
+        }
+        activate(A, H);
+      }
+      float u[DO][4];
+      out_fwd(P + offL, P + offL + DO * w, w, g, H, u);
+
+      // ---- loss terms and output seeds
+      float ub[DO][4], loss[kLossTerms];
+      epilogue(ka, it, nd, pt, valid, u, ub, loss);
+#pragma unroll
+      for (int t = 0; t < kLossTerms; ++t) {
+        float v = g == 0 ? loss[t] : 0.f;
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        if (lane == 0) sRed[wave * kLossTerms + t] = v;
+      }
+      if (g == 0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < DO; ++c) sU[(s * 3 + c) * TP + tp] = ub[c][s];
+      }
+
+      // ---- output layer adjoint: g^D = W^{LT} ubar; dW^L, db^L
+      Streams G;
+      {
+        const float* WL = P + offL;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int j = 16 * mb + 4 * g + i;
+            float wl[DO];
+#pragma unroll
+            for (int c = 0; c < DO; ++c) wl[c] = j < w ? WL[c * w + j] : 0.f;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              float acc = 0.f;
+#pragma unroll
+              for (int c = 0; c < DO; ++c) acc = fmaf(wl[c], ub[c][s], acc);
+              G[s][mb][i] = acc;
+            }
+          }
+        }
+      }
+      float accL[KL];
+#pragma unroll
+      for (int r = 0; r < KL; ++r) accL[r] = 0.f;
+      float accB = 0.f;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sH[(16 * mb + 4 * g + i) * TPS + tp] = H[s][mb][i];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < KL; ++r) {
+          const int t = tid + r * NT;
+          if (t < DO * WP) {
+            const int c = t / WP, j = t - (t / WP) * WP;
+            accL[r] = row_dot(sU + (s * 3 + c) * TP, sH + j * TPS, accL[r]);
+          }
+        }
+        if (s == 0 && tid < DO) accB = row_sum(sU + tid * TP);
+      }
+#pragma unroll
+      for (int r = 0; r < KL; ++r) {
+        const int t = tid + r * NT;
+        if (t < DO * WP) {
+          const int c = t / WP, j = t - (t / WP) * WP;
+          if (j < w) {
+            float* dst = R + offL + c * w + j;
+            *dst = first ? accL[r] : *dst + accL[r];
+          }
+        }
+      }
+      if (tid < DO) {
+        float* dst = R + offL + DO * w + tid;
+        *dst = first ? accB : *dst + accB;
+      }
+      if (tid < kLossTerms) {
+        float v = 0.f;
+        for (int wv = 0; wv < kWaves; ++wv) v += sRed[wv * kLossTerms + tid];
+        v *= it.inv_n;
+        float* dst = ka.loss_part + (int64_t)it.lrow * kLossTerms + tid;
+        *dst = first ? v : *dst + v;
+      }
+
+      // ---- hidden layers, top down
+      if (D >= 2) {
+        Streams Ak;
+        {
+          const f4* sb = stash_base(slot, D, wave, lane);
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) Ak[s][mb] = sb[(s * MB + mb) * 64];
+        }
+        for (int k = D; k >= 2; --k) {
+          const int64_t off = 3 * w + (int64_t)(k - 2) * (w * w + w);
+          // abar^k from the stashed a^k and the incoming g^k
+          Streams Ab;
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              float a0, a1, a2, a3;
+              tanh_adj<S2>(Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i], G[0][mb][i],
+                           G[1][mb][i], G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
+              Ab[0][mb][i] = a0;
+              Ab[1][mb][i] = a1;
+              Ab[2][mb][i] = a2;
+              Ab[3][mb][i] = a3;
+            }
+          }
+          // a^{k-1}: stashed, or recomputed for layer 1
+          if (k - 1 >= 2) {
+            const f4* sb = stash_base(slot, k - 1, wave, lane);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+              for (int mb = 0; mb < MB; ++mb) Ak[s][mb] = sb[(s * MB + mb) * 64];
+          } else {
+            layer1(P, w, x, y, g, Ak);
+          }
+          __syncthreads();
+          stage_wt(sW, P + off, w);
+          // per stream: g^{k-1}_s = W^{kT} abar^k_s, then the stream's share of
+          // dW^k = sum_{points, streams} abar^k h^{k-1 T}; db^k = sum_points abar^k_0
+          f4 dacc[NB];
+#pragma unroll
+          for (int r = 0; r < NB; ++r) dacc[r] = f4{0.f, 0.f, 0.f, 0.f};
+          float dbias = 0.f;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            __builtin_amdgcn_sched_barrier(0);
+            f4 Hs[MB];
+            activate_stream(Ak, s, Hs);
+            __syncthreads();
+            hidden_bwd_stream(sW, g, pc, Ab[s], G[s]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                sA[(16 * mb + 4 * g + i) * TPS + tp] = Ab[s][mb][i];
+                sH[(16 * mb + 4 * g + i) * TPS + tp] = Hs[mb][i];
+              }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+              const int b = wave + r * kWaves;
+              if (b < MB * MB) {
+                const int mb = b / MB, jb = b - (b / MB) * MB;
+#pragma unroll
+                for (int gq = 0; gq < TP / 16; ++gq) {
+                  const f4 av = *reinterpret_cast<const f4*>(&sA[(16 * mb + pc) * TPS + 16 * gq + 4 * g]);
+                  const f4 hv = *reinterpret_cast<const f4*>(&sH[(16 * jb + pc) * TPS + 16 * gq + 4 * g]);
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) dacc[r] = mma(av[i], hv[i], dacc[r]);
+                }
+              }
+            }
+            if (s == 0 && tid < WP) dbias = row_sum(sA + tid * TPS);
+          }
+#pragma unroll
+          for (int r = 0; r < NB; ++r) {
+            const int b = wave + r * kWaves;
+            if (b < MB * MB) {
+              const int mb = b / MB, jb = b - (b / MB) * MB;
+              const int j = 16 * jb + pc;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int m = 16 * mb + 4 * g + i;
+                if (m < w && j < w) {
+                  float* dst = R + off + m * w + j;
+                  *dst = first ? dacc[r][i] : *dst + dacc[r][i];
+                }
+              }
+            }
+          }
+          if (tid < w) {
+            float* dst = R + off + w * w + tid;
+            *dst = first ? dbias : *dst + dbias;
+          }
+        }
+      }
+
+      // ---- layer 1: abar^1 from a^1 and g^1; dW^1 and db^1 are sums over points
+      {
+        Streams A1;
+        layer1(P, w, x, y, g, A1);
+        Streams Ab;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float a0, a1, a2, a3;
+            tanh_adj<S2>(A1[0][mb][i], A1[1][mb][i], A1[2][mb][i], A1[3][mb][i], G[0][mb][i], G[1][mb][i],
+                         G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
+            Ab[0][mb][i] = a0;
+            Ab[1][mb][i] = a1;
+            Ab[2][mb][i] = a2;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            sA[(16 * mb + 4 * g + i) * TPS + tp] = Ab[0][mb][i];
+            sH[(16 * mb + 4 * g + i) * TPS + tp] = Ab[1][mb][i];
+          }
+        __syncthreads();
+        float dw0 = 0.f, dw1 = 0.f, db = 0.f;
+        if (tid < WP) {
+          dw0 = row_dot_plus(sA + tid * TPS, sX, sH + tid * TPS);
+          db = row_sum(sA + tid * TPS);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sH[(16 * mb + 4 * g + i) * TPS + tp] = Ab[2][mb][i];
+        __syncthreads();
+        if (tid < WP) dw1 = row_dot_plus(sA + tid * TPS, sX + TP, sH + tid * TPS);
+        if (tid < w) {
+          float* d0 = R + 2 * tid;
+          float* d1 = R + 2 * tid + 1;
+          float* d2 = R + 2 * w + tid;
+          *d0 = first ? dw0 : *d0 + dw0;
+          *d1 = first ? dw1 : *d1 + dw1;
+          *d2 = first ? db : *d2 + db;
+        }
+      }
+    }
+  }
+};
+
+template <int WP, int PDE>
+constexpr int lds_train_floats() {
+  return WP * (WP + 4) + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms;
+}
+
+template <int WPMAX, int PDE, bool TRAIN>
+__device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
+                                         float* slot) {
+#define DDP_CASE(WPV)                                                          \
+  case WPV:                                                                    \
+    if constexpr (WPV <= WPMAX) {                                              \
+      if constexpr (TRAIN) Tile<WPV, PDE>::run_train(ka, it, nd, lds, slot);   \
+      else Tile<WPV, PDE>::run_values(ka, it, nd, lds);                        \
+    }                                                                          \
+    break;
+  switch (nd.wclass) {
+    DDP_CASE(16)
+    DDP_CASE(32)
+    DDP_CASE(48)
+    DDP_CASE(64)
+    DDP_CASE(80)
+    DDP_CASE(96)
+    DDP_CASE(112)
+    default: break;
+  }
+#undef DDP_CASE
+}
+
+// First kernel of a step: interface values of every network (the exchange of
+// Algorithm 1 becomes this kernel's output buffer); block 0 also settles the
+// Adam step counter and clears the work counters.
+template <int WPMAX, int PDE>
+__global__ __launch_bounds__(NT) void k_values(KArgs ka) {
+  extern __shared__ float lds[];
+  if (ka.prologue && blockIdx.x == 0 && threadIdx.x == 0) {
+    ka.tstate[0] += ka.tstate[1];
+    ka.tstate[1] = 0;
+    for (int i = 0; i < ka.n_counters; ++i) ka.counters_all[i] = 0;
+  }
+  if ((int)blockIdx.x >= ka.n_items) return;
+  const Item it = ka.items[blockIdx.x];
+  const NetDesc nd = ka.nets[it.q];
+  dispatch<WPMAX, PDE, false>(ka, it, nd, lds, nullptr);
+}
+
+// Persistent kernel: workgroups pull items (in descending cost order) from a
+// device counter until the list is drained.
+template <int WPMAX, int PDE>
+__global__ __launch_bounds__(NT) void k_train(KArgs ka) {
+  extern __shared__ float lds[];
+  __shared__ int s_item;
+  float* slot = ka.scratch + (int64_t)blockIdx.x * ka.scratch_slot;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(ka.counter, 1);
+    __syncthreads();
+    const int idx = s_item;
+    __syncthreads();
+    if (idx >= ka.n_items) break;
+    const Item it = ka.items[idx];
+    const NetDesc nd = ka.nets[it.q];
+    dispatch<WPMAX, PDE, true>(ka, it, nd, lds, slot);
+  }
+}
+
+// Sum each subdomain's gradient partial rows in a fixed order, then write the
+// gradient and/or apply Adam (Kingma-Ba, bias corrected); block 0 also sums
+// the loss rows and flags non-finite losses.
+__global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
+  const int64_t p0 = ra.sd_poff[ra.q_begin], p1 = ra.sd_poff[ra.q_end];
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float tstep = (float)(ra.tstate[0] + 1);
+  const float bc1 = 1.f - powf(b1, tstep);
+  const float bc2 = 1.f - powf(b2, tstep);
+  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int q = ra.q_begin;
+    while (ra.sd_poff[q + 1] <= i) ++q;
+    const int64_t li = i - ra.sd_poff[q];
+    float s = 0.f;
+    for (int r = ra.sd_row_ptr[q]; r < ra.sd_row_ptr[q + 1]; ++r) s += ra.partial[ra.row_prow[ra.sd_rows[r]] + li];
+    if (ra.grad_out) ra.grad_out[i] = s;
+    if (ra.do_adam) {
+      const float m = b1 * ra.adam_m[i] + (1.f - b1) * s;
+      const float v = b2 * ra.adam_v[i] + (1.f - b2) * s * s;
+      ra.adam_m[i] = m;
+      ra.adam_v[i] = v;
+      const float mh = m / bc1;
+      const float vh = v / bc2;
+      ra.params[i] -= ra.nets[q].lr * mh / (sqrtf(vh) + eps);
+    }
+  }
+  if (blockIdx.x == 0) {
+    for (int q = ra.q_begin + threadIdx.x; q < ra.q_end; q += blockDim.x) {
+      float t[kLossTerms] = {0.f, 0.f, 0.f, 0.f};
+      for (int r = ra.sd_row_ptr[q]; r < ra.sd_row_ptr[q + 1]; ++r) {
+        const float* lp = ra.loss_part + (int64_t)ra.row_lrow[ra.sd_rows[r]] * kLossTerms;
+        for (int k = 0; k < kLossTerms; ++k) t[k] += lp[k];
+      }
+      const NetDesc nd = ra.nets[q];
+      float J = 0.f;
+      for (int k = 0; k < kLossTerms; ++k) J += nd.loss_w[k] * t[k];
+      if (ra.loss_out) {
+        ra.loss_out[q * 5] = J;
+        for (int k = 0; k < kLossTerms; ++k) ra.loss_out[q * 5 + 1 + k] = t[k];
+      }
+      if (!isfinite(J)) ra.flags[0] = 1;
+    }
+    if (ra.do_adam && threadIdx.x == 0) ra.tstate[1] = 1;
+  }
+}
+
+// Stitched solution (Eq. FSol): average of the owning networks' outputs.
+__global__ __launch_bounds__(256) void k_eval(const float* params, const NetDesc* nets, int n_sd, int n,
+                                              const float* xy, const int* owner, float* out, int d_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc[kMaxOut] = {0.f, 0.f, 0.f};
+  int cnt = 0;
+  float h[kMaxWidth], h2[kMaxWidth];
+  for (int o = 0; o < 4; ++o) {
+    const int q = owner[4 * i + o];
+    if (q < 0 || q >= n_sd) continue;
+    ++cnt;
+    const NetDesc nd = nets[q];
+    const float* P = params + nd.poff;
+    const int w = nd.width;
+    const float x = xy[2 * i], y = xy[2 * i + 1];
+    for (int m = 0; m < w; ++m) h[m] = tanhf(fmaf(P[2 * m], x, fmaf(P[2 * m + 1], y, P[2 * w + m])));
+    int64_t off = 3 * w;
+    for (int k = 2; k <= nd.depth; ++k) {
+      for (int m = 0; m < w; ++m) {
+        float a = P[off + w * w + m];
+        for (int j = 0; j < w; ++j) a = fmaf(P[off + m * w + j], h[j], a);
+        h2[m] = tanhf(a);
+      }
+      for (int m = 0; m < w; ++m) h[m] = h2[m];
+      off += w * w + w;
+    }
+    for (int c = 0; c < nd.d_out; ++c) {
+      float a = P[off + nd.d_out * w + c];
+      for (int j = 0; j < w; ++j) a = fmaf(P[off + c * w + j], h[j], a);
+      acc[c] += a;
+    }
+  }
+  for (int c = 0; c < d_out; ++c) out[(int64_t)i * d_out + c] = cnt ? acc[c] / cnt : 0.f;
+}
+
+#ifndef DDP_KERNELS_ONLY
+// ---------------------------------------------------------------------------
+// host-side launchers
+
+static int wclass_index(int wpmax) {
+  switch (wpmax) {
+    case 16: return 0;
+    case 32: return 1;
+    case 48: return 2;
+    case 64: return 3;
+    case 80: return 4;
+    case 96: return 5;
+    case 112: return 6;
+  }
+  return -1;
+}
+
+template <int PDE>
+struct KTable {
+  static const void* values[7];
+  static const void* train[7];
+  static int lds[7];
+};
+#define DDP_ROW(PDE)                                                                            \
+  template <> const void* KTable<PDE>::values[7] = {                                            \
+      (const void*)k_values<16, PDE>, (const void*)k_values<32, PDE>, (const void*)k_values<48, PDE>, \
+      (const void*)k_values<64, PDE>, (const void*)k_values<80, PDE>, (const void*)k_values<96, PDE>, \
+      (const void*)k_values<112, PDE>};                                                         \
+  template <> const void* KTable<PDE>::train[7] = {                                             \
+      (const void*)k_train<16, PDE>, (const void*)k_train<32, PDE>, (const void*)k_train<48, PDE>, \
+      (const void*)k_train<64, PDE>, (const void*)k_train<80, PDE>, (const void*)k_train<96, PDE>, \
+      (const void*)k_train<112, PDE>};                                                          \
+  template <> int KTable<PDE>::lds[7] = {                                                       \
+      lds_train_floats<16, PDE>(), lds_train_floats<32, PDE>(), lds_train_floats<48, PDE>(),    \
+      lds_train_floats<64, PDE>(), lds_train_floats<80, PDE>(), lds_train_floats<96, PDE>(),    \
+      lds_train_floats<112, PDE>()};
+DDP_ROW(PDE_POISSON)
+DDP_ROW(PDE_BURGERS)
+DDP_ROW(PDE_NS)
+#undef DDP_ROW
+
+static const void* pick(int pde, int wpmax, bool train) {
+  const int c = wclass_index(wpmax);
+  if (c < 0) return nullptr;
+  switch (pde) {
+    case PDE_POISSON: return train ? KTable<PDE_POISSON>::train[c] : KTable<PDE_POISSON>::values[c];
+    case PDE_BURGERS: return train ? KTable<PDE_BURGERS>::train[c] : KTable<PDE_BURGERS>::values[c];
+    case PDE_NS: return train ? KTable<PDE_NS>::train[c] : KTable<PDE_NS>::values[c];
+  }
+  return nullptr;
+}
+
+size_t lds_bytes(int pde, int wpmax, bool train) {
+  const int c = wclass_index(wpmax);
+  if (c < 0) return 0;
+  if (!train) return (size_t)wpmax * (wpmax + 4) * sizeof(float);
+  int f = 0;
+  switch (pde) {
+    case PDE_POISSON: f = KTable<PDE_POISSON>::lds[c]; break;
+    case PDE_BURGERS: f = KTable<PDE_BURGERS>::lds[c]; break;
+    case PDE_NS: f = KTable<PDE_NS>::lds[c]; break;
+  }
+  return (size_t)f * sizeof(float);
+}
+
+int64_t scratch_slot_floats(int wpmax) {
+  return (int64_t)(kMaxDepth - 1) * kWaves * 4 * (wpmax / 16) * 64 * 4;
+}
+
+hipError_t launch_values(int pde, int wpmax, const KArgs& ka, hipStream_t st) {
+  const void* fn = pick(pde, wpmax, false);
+  if (!fn) return hipErrorInvalidValue;
+  KArgs a = ka;
+  void* args[] = {&a};
+  const int grid = ka.n_items > 0 ? ka.n_items : 1;
+  return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds_bytes(pde, wpmax, false), st);
+}
+
+hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream_t st) {
+  const void* fn = pick(pde, wpmax, true);
+  if (!fn) return hipErrorInvalidValue;
+  KArgs a = ka;
+  void* args[] = {&a};
+  return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds_bytes(pde, wpmax, true), st);
+}
+
+hipError_t train_occupancy(int pde, int wpmax, int* blocks_per_cu) {
+  const void* fn = pick(pde, wpmax, true);
+  if (!fn) return hipErrorInvalidValue;
+  const size_t lds = lds_bytes(pde, wpmax, true);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(pick(pde, wpmax, false), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_bytes(pde, wpmax, false));
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, NT, lds);
+}
+
+hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, st, ra);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(const float* params, const NetDesc* nets, int n_sd, int n, const float* xy, const int* owner,
+                       float* out, int d_out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eval, dim3((n + 255) / 256), dim3(256), 0, st, params, nets, n_sd, n, xy, owner, out, d_out);
+  return hipGetLastError();
+}
+
+#endif  // DDP_KERNELS_ONLY
+}  // namespace ddp

@@ -1,0 +1,50 @@
+"""Helpers shared by the GPU parity tests (comparison rules only)."""
+import numpy as np
+
+import oracle
+
+# "1e-5 relative": each loss term within 1e-5 * max(|term|, 1e-3 * J_q); each
+# subdomain gradient within 1e-5 * ||g_q|| in the 2-norm, also per layer tensor.
+LOSS_RTOL = 1e-5
+GRAD_RTOL = 1e-5
+
+
+def layer_slices(widths):
+    out, off = [], 0
+    for k in range(1, len(widths)):
+        n = widths[k] * widths[k - 1]
+        out.append(slice(off, off + n))
+        off += n
+        out.append(slice(off, off + widths[k]))
+        off += widths[k]
+    return out
+
+
+def compare(prob, params, lt_gpu, g_gpu, loss_rtol=LOSS_RTOL, grad_rtol=GRAD_RTOL, per_layer=True):
+    """Compare GPU loss terms / gradients with the FP64 oracle; returns the
+    worst relative errors (loss, grad) and raises AssertionError on failure."""
+    terms, grads = oracle.loss_and_grad(prob, params)
+    lt = np.asarray(lt_gpu, np.float64)
+    worst_l, worst_g = 0.0, 0.0
+    for q in range(prob.n_sd):
+        J = abs(terms[q, 0])
+        for k in range(5):
+            scale = max(abs(terms[q, k]), 1e-3 * J, 1e-30)
+            err = abs(lt[q, k] - terms[q, k]) / scale
+            worst_l = max(worst_l, err)
+            assert err <= loss_rtol, f"sd {q} term {k}: gpu {lt[q, k]!r} oracle {terms[q, k]!r} rel {err:.3e}"
+        g = np.asarray(g_gpu[q], np.float64)
+        ref = grads[q]
+        nref = np.linalg.norm(ref)
+        err = np.linalg.norm(g - ref) / max(nref, 1e-30)
+        worst_g = max(worst_g, err)
+        assert err <= grad_rtol, f"sd {q} grad rel {err:.3e} (|g|={nref:.3e})"
+        if per_layer:
+            for k, sl in enumerate(layer_slices(prob.subdomains[q].widths)):
+                r = ref[sl]
+                nr = np.linalg.norm(r)
+                if nr < 1e-6 * nref:
+                    continue
+                e = np.linalg.norm(g[sl] - r) / nr
+                assert e <= 10 * grad_rtol, f"sd {q} tensor {k} rel {e:.3e}"
+    return worst_l, worst_g

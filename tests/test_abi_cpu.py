@@ -1,0 +1,134 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+validates its inputs and builds a consistent plan (no GPU needed)."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2104_10013_amd import ddpinn, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ddpinn.h")).read()
+    return sorted(set(re.findall(r"\b(ddp_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ddpinn.load_library()
+    decl = _declared()
+    assert len(decl) >= 18
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(ddpinn.EXPORTED) == decl
+
+
+def _plan(prob, tmp_path, **kw):
+    pb = ddpinn.Problem(prob, plan_only=True, **kw)
+    path = tmp_path / "plan.json"
+    pb.plan_dump(path)
+    d = json.load(open(path))
+    pb.close()
+    return d
+
+
+@pytest.mark.parametrize("name", ["c1_cpinn_poisson", "c2_xpinn_poisson", "c3_cpinn_burgers", "c4_xpinn_kovasznay"])
+def test_plan_covers_every_point_once(name, tmp_path):
+    prob = W.make_problem(name, seed=0, scale=0.3)
+    d = _plan(prob, tmp_path, chunk_points=100)
+    items = np.array(d["train_items"])
+    q, kind, begin, count, iface, side = (items[:, i] for i in range(6))
+    assert (count > 0).all() and (count <= 128).all()   # chunk rounded up to the 64-point tile
+    # residual and data points: each packed index in exactly one item
+    for k, total in ((0, d["n_res"]), (1, d["n_dat"])):
+        cover = np.zeros(total, int)
+        for b, c in zip(begin[kind == k], count[kind == k]):
+            cover[b:b + c] += 1
+        assert (cover == 1).all()
+    # interface points: once per side
+    cover = np.zeros((d["n_if"], 2), int)
+    for b, c, s in zip(begin[kind == 2], count[kind == 2], side[kind == 2]):
+        cover[b:b + c, s] += 1
+    assert (cover == 1).all()
+    # items of an interface side belong to that side's subdomain
+    for row in items[kind == 2]:
+        e = d["ifaces"][row[4]]
+        assert row[0] == (e["a"] if row[5] == 0 else e["b"])
+    # descending cost order (fused path)
+    nets = d["nets"]
+    cost = [c * (1 + (nets[qq]["depth"] - 1) * nets[qq]["wclass"] ** 2 * 24 + 40 * nets[qq]["wclass"])
+            for qq, c in zip(q, count)]
+    assert all(cost[i] >= cost[i + 1] for i in range(len(cost) - 1))
+    # partial rows are disjoint and sized to the subdomain's parameters
+    prow = items[:, 7]
+    order = np.argsort(prow)
+    ends = prow[order] + np.array([nets[qq]["n_params"] for qq in q[order]])
+    assert (ends[:-1] <= prow[order][1:]).all() and ends[-1] == d["partial_floats"]
+    # every item appears once in the per-subdomain row lists
+    rows = np.array(d["sd_rows"])
+    assert sorted(rows.tolist()) == list(range(len(items)))
+    ptr = d["sd_row_ptr"]
+    for qq in range(len(nets)):
+        assert (q[rows[ptr[qq]:ptr[qq + 1]]] == qq).all()
+    # parameter offsets follow the canonical layout sizes
+    for qq, s in enumerate(prob.subdomains):
+        assert nets[qq]["n_params"] == W.param_count(s.widths)
+        assert nets[qq]["wclass"] % 16 == 0 and nets[qq]["wclass"] >= s.widths[1]
+
+
+def _raw():
+    L = ddpinn.load_library()
+    import ctypes
+    h = ctypes.c_void_p()
+    coef = (ctypes.c_double * 1)(1.0)
+    assert L.ddp_create(ctypes.byref(h), 1, 0, coef, 0) == 0
+    return L, h, ctypes
+
+
+def test_input_validation_codes():
+    L, h, ct = _raw()
+    lw = (ct.c_float * 4)(1, 1, 1, 1)
+    sid = ct.c_int()
+    good = (ct.c_int * 4)(2, 8, 8, 1)
+    nl = (ct.c_int * 1)(4)
+    assert L.ddp_add_subdomain(h, 1, nl, good, lw, 1e-3, ct.byref(sid)) == 0
+    assert L.ddp_add_subdomain(h, 1, nl, good, lw, 1e-3, ct.byref(sid)) == 0
+    bad = (ct.c_int * 4)(2, 8, 9, 1)   # uneven hidden widths
+    assert L.ddp_add_subdomain(h, 1, nl, bad, lw, 1e-3, ct.byref(sid)) == ddpinn.DDP_EINVAL
+    wide = (ct.c_int * 4)(2, 200, 200, 1)
+    assert L.ddp_add_subdomain(h, 1, nl, wide, lw, 1e-3, ct.byref(sid)) == ddpinn.DDP_EINVAL
+    two = (ct.c_int * 1)(4)
+    assert L.ddp_add_subdomain(h, 2, two, good, lw, 1e-3, ct.byref(sid)) == ddpinn.DDP_EINVAL
+    xy = np.array([[0.1, 0.2], [np.nan, 0.3]], np.float32)
+    f = np.zeros(2, np.float32)
+    rc = L.ddp_set_points(h, 0, 0, 2, xy.ctypes.data_as(ct.c_void_p), f.ctypes.data_as(ct.c_void_p), 0)
+    assert rc == ddpinn.DDP_EINVAL and b"non-finite" in L.ddp_last_error()
+    xy = np.array([[0.1, 0.2], [0.4, 0.3]], np.float32)
+    nrm = (ct.c_float * 2)(1, 0)
+    assert L.ddp_add_interface(h, 0, 5, 2, xy.ctypes.data_as(ct.c_void_p), nrm, 0, None) == ddpinn.DDP_EINVAL
+    assert L.ddp_add_interface(h, 1, 1, 2, xy.ctypes.data_as(ct.c_void_p), nrm, 0, None) == ddpinn.DDP_EINVAL
+    assert L.ddp_add_interface(h, 0, 1, 2, xy.ctypes.data_as(ct.c_void_p), nrm, 0, None) == 0
+    assert L.ddp_set_option(h, 99, 1) == ddpinn.DDP_EINVAL
+    # calls that need a finalized problem
+    assert L.ddp_step(h, 1, None) == ddpinn.DDP_ESTATE
+    assert L.ddp_sync(h) == ddpinn.DDP_ESTATE
+    assert L.ddp_plan_dump(h, b"/tmp/x.json") == ddpinn.DDP_ESTATE
+    assert L.ddp_plan(h) == 0
+    assert L.ddp_destroy(h) == 0
+
+
+def test_create_rejects_bad_combinations():
+    L = ddpinn.load_library()
+    import ctypes as ct
+    h = ct.c_void_p()
+    c = (ct.c_double * 1)(40.0)
+    assert L.ddp_create(ct.byref(h), 0, 2, c, 1) == ddpinn.DDP_EINVAL   # cPINN + NS
+    assert L.ddp_create(ct.byref(h), 1, 1, c, 0) == ddpinn.DDP_EINVAL   # Burgers without nu
+    assert L.ddp_create(ct.byref(h), 3, 0, c, 0) == ddpinn.DDP_EINVAL
+    neg = (ct.c_double * 1)(-1.0)
+    assert L.ddp_create(ct.byref(h), 1, 2, neg, 1) == ddpinn.DDP_EINVAL
+    assert L.ddp_create(ct.byref(h), 1, 2, c, 1) == 0
+    assert L.ddp_destroy(h) == 0
