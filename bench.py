@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark: one training step of the 16-subdomain XPINN Poisson workload
+(4x4 subdomains, per-subdomain widths from {20,40,60,80}, 3-6 hidden layers,
+2k-20k residual points each, 200 points per interface) on one GPU.
+
+Prints one JSON line.  `value` is residual points per second of the fused
+step (all subdomains in one persistent launch, replayed as a HIP graph);
+the per-subdomain launch path is timed on the same inputs alongside.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+METRIC = "residual points/s per train step (fused vs per-subdomain), 16-subdomain XPINN"
+WORKLOAD = "c2_xpinn_poisson"
+
+
+def algorithmic_flops(prob):
+    """MFMA-countable work of one step: the hidden-to-hidden products
+    (unpadded widths), forward (2 flops per MAC) plus the two backward
+    contractions (g = W^T abar and dW), times the Taylor streams each point
+    class carries: residual 4, data 1, interface 4 (XPINN) or 2 (cPINN) per
+    network evaluating it."""
+    s_if = 4 if prob.method == "xpinn" else 2
+    n_if = [0] * prob.n_sd
+    for e in prob.interfaces:
+        n_if[e.a] += e.xy.shape[0]
+        n_if[e.b] += e.xy.shape[0]
+    total = 0.0
+    for q, s in enumerate(prob.subdomains):
+        w = s.widths[1]
+        depth = len(s.widths) - 2
+        cols = 4 * s.res_xy.shape[0] + 1 * s.bnd_xy.shape[0] + s_if * n_if[q]
+        total += 6.0 * cols * (depth - 1) * w * w
+    return total
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "ddp_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2104_10013_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(n_launch_units):
+    """HBM bytes per launch of the train kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "k_train_c2_xpinn_poisson_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_sha") != kernel_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(prob, reps=3):
+    """The FP64 oracle (loss_and_grad + Adam of every subdomain) timed on the
+    host's cores; the sample is `reps` full steps of the same workload."""
+    import torch
+    import oracle
+    params = [s.params.astype(np.float64) for s in prob.subdomains]
+    ms = [np.zeros_like(p) for p in params]
+    vs = [np.zeros_like(p) for p in params]
+
+    def one_step(t):
+        _, grads = oracle.loss_and_grad(prob, params)
+        for q in range(prob.n_sd):
+            oracle.adam_step(params[q], ms[q], vs[q], grads[q], t, prob.subdomains[q].lr)
+
+    one_step(1)  # warm-up
+    times = []
+    for r in range(reps):
+        t0 = time.perf_counter()
+        one_step(r + 2)
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    return {"value": prob.n_residual() / med, "unit": "residual points/s", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": f"{reps} full FP64 oracle steps (loss, gradient, Adam) of the same "
+                                        f"workload, median {med:.2f} s/step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--chunk-points", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
+              f"all subdomains on a single GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_10013_amd import ddpinn, workloads as W
+
+    prob = W.make_problem(WORKLOAD, seed=args.seed)
+    n_res = prob.n_residual()
+    flops = algorithmic_flops(prob)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def time_path(fused):
+        pb = ddpinn.Problem(prob, fused=fused, device=dev, stream=stream, chunk_points=args.chunk_points)
+        pb.step(args.warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pb.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        pb.sync()
+        return pb, ms
+
+    pf, ms_fused = time_path(True)
+    print(f"# fused: {ms_fused:.4f} ms/step", file=sys.stderr, flush=True)
+    kt = pf.time_kernels(max(10, min(args.steps, 100)))
+    print(f"# kernels: {kt}", file=sys.stderr, flush=True)
+    pf.close()
+    plain = None
+    if not args.no_plain:
+        pp, ms_plain = time_path(False)
+        pp.close()
+        plain = {"value": n_res / (ms_plain * 1e-3), "ms_per_step": ms_plain,
+                 "steps_per_s": 1e3 / ms_plain}
+        print(f"# plain: {ms_plain:.4f} ms/step", file=sys.stderr, flush=True)
+
+    achieved = flops / (kt["train_ms"] * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": traffic_from_profile(1),
+            "kernel": "k_train", "kernel_ms": kt["train_ms"], "algorithmic_flop_per_launch": flops}
+    out = {
+        "metric": METRIC, "value": n_res / (ms_fused * 1e-3), "unit": "residual points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_fused, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "xpinn_poisson2d_4x4_uneven (16 subdomains, widths {20,40,60,80}, 3-6 hidden "
+                               "layers, U[2k,20k] residual pts, 200 pts/interface)",
+                   "seed": args.seed, "n_residual": n_res, "parallelism": "single GPU, fused persistent launch"},
+        "steps_per_s": 1e3 / ms_fused,
+        "plain": plain,
+        "speedup_vs_plain": (plain["ms_per_step"] / ms_fused) if plain else None,
+        "kernel_ms": kt,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
