@@ -16,15 +16,47 @@ enum Pde { PDE_POISSON = 0, PDE_BURGERS = 1, PDE_NS = 2 };
 enum Method { METHOD_CPINN = 0, METHOD_XPINN = 1 };
 
 // One network: widths 2 -> w (x depth) -> d_out.
+//
+// Besides the canonical parameters (per layer W[out][in] then b[out]) every
+// network has a zero-padded "kernel layout" copy, rewritten by the Adam kernel
+// after each update, with WP = wclass, WS = WP + 4 (LDS row stride):
+//   [WP][4]            layer 1: (W1[m][0], W1[m][1], b1[m], 0)
+//   per hidden layer k = 2..D:
+//     [WP][WS]         W^k            [WP][WS]  W^k transposed    [WP]  b^k
+//   [d_out][WP]        output W^L     [4]       b^L
+// Gradient partial rows use the same order without the transposes and
+// without the row padding:  [WP][4], per hidden layer [WP][WP] + [WP],
+// [d_out][WP] + [4].
 struct NetDesc {
   int width;        // hidden width w
   int depth;        // hidden layers D
   int d_out;        // outputs
   int wclass;       // padded width class (multiple of 16)
-  int64_t poff;     // offset of this network's parameters in the flat buffer
+  int64_t poff;     // offset of the canonical parameters in the flat buffer
   int n_params;
+  int64_t koff;     // offset of the kernel-layout copy
+  int ksize;        // floats of the kernel-layout copy
+  int gsize;        // floats of one gradient partial row
   float loss_w[4];  // W_u, W_F, W_I, W_flux | W_IF
   float lr;
+};
+
+// kernel-layout and partial-row offsets (floats) of a network
+struct Layout {
+  int WP, WS, D, DO;
+  __host__ __device__ Layout(int wp, int d, int dout) : WP(wp), WS(wp + 4), D(d), DO(dout) {}
+  __host__ __device__ int k_hidden(int k) const { return 4 * WP + (k - 2) * (2 * WP * WS + WP); }
+  __host__ __device__ int k_w(int k) const { return k_hidden(k); }
+  __host__ __device__ int k_wt(int k) const { return k_hidden(k) + WP * WS; }
+  __host__ __device__ int k_b(int k) const { return k_hidden(k) + 2 * WP * WS; }
+  __host__ __device__ int k_out() const { return k_hidden(D + 1); }
+  __host__ __device__ int k_bout() const { return k_out() + DO * WP; }
+  __host__ __device__ int k_size() const { return k_bout() + 4; }
+  __host__ __device__ int g_w(int k) const { return 4 * WP + (k - 2) * (WP * WP + WP); }
+  __host__ __device__ int g_b(int k) const { return g_w(k) + WP * WP; }
+  __host__ __device__ int g_out() const { return g_w(D + 1); }
+  __host__ __device__ int g_bout() const { return g_out() + DO * WP; }
+  __host__ __device__ int g_size() const { return g_bout() + 4; }
 };
 
 // One work item: a contiguous range of one point set evaluated by one network.
@@ -48,7 +80,7 @@ struct IfaceDesc {
 
 // Arguments of the per-point kernels.
 struct KArgs {
-  const float* params;
+  const float* kparams;   // kernel-layout parameter copies
   const NetDesc* nets;
   const Item* items;
   int n_items;
@@ -77,6 +109,7 @@ struct KArgs {
 // Arguments of the reduction / Adam kernel.
 struct RArgs {
   float* params;
+  float* kparams;
   float* adam_m;
   float* adam_v;
   const float* partial;

@@ -74,7 +74,7 @@ struct ddp_problem {
   int n_eq = 1, d_out = 1, n_val = 2;
   std::vector<HostSd> sds;
   std::vector<HostIf> ifs;
-  int64_t chunk_points = 256;
+  int64_t chunk_points = 1024;  // upper bound of points per work item
   int blocks_per_cu = 0;  // 0: from the occupancy query
 
   // plan
@@ -83,6 +83,8 @@ struct ddp_problem {
   int wpmax = 16;
   std::vector<NetDesc> nets;
   std::vector<int64_t> sd_poff;  // n_sd + 1
+  int64_t kparam_floats = 0;
+  int plan_slots = 512;          // workgroups the plan balances for
   std::vector<Item> titems;      // train items (fused: descending cost; plain: grouped by q)
   std::vector<Item> vitems;      // interface-value items, grouped by q
   std::vector<int> t_begin, v_begin;  // per q ranges (plain path), n_sd + 1
@@ -98,7 +100,7 @@ struct ddp_problem {
   hipStream_t cap_stream = nullptr;  // private stream used for graph capture
   int n_slots = 0;
   int64_t slot_floats = 0;
-  float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr;
+  float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_kparams = nullptr;
   int *d_tstate = nullptr, *d_flags = nullptr, *d_counters = nullptr;
   int n_counters = 0;
   NetDesc* d_nets = nullptr;
@@ -166,11 +168,12 @@ int build_plan(ddp_problem* p) {
   if (n_sd == 0) return fail(DDP_EINVAL, "no subdomains");
   for (const HostIf& f : p->ifs)
     if (f.a >= n_sd || f.b >= n_sd) return fail(DDP_EINVAL, "interface names an unknown subdomain");
-  int64_t chunk = std::max<int64_t>(kTilePts, (p->chunk_points + kTilePts - 1) / kTilePts * kTilePts);
+  const int64_t chunk_max = std::max<int64_t>(kTilePts, (p->chunk_points + kTilePts - 1) / kTilePts * kTilePts);
 
   // networks and parameter offsets
   p->nets.assign(n_sd, NetDesc{});
   p->sd_poff.assign(n_sd + 1, 0);
+  p->kparam_floats = 0;
   p->wpmax = 16;
   for (int q = 0; q < n_sd; ++q) {
     const HostSd& s = p->sds[q];
@@ -181,6 +184,11 @@ int build_plan(ddp_problem* p) {
     nd.wclass = width_class(nd.width);
     nd.poff = p->sd_poff[q];
     nd.n_params = (int)net_param_count(s.widths);
+    const Layout L(nd.wclass, nd.depth, nd.d_out);
+    nd.koff = p->kparam_floats;
+    nd.ksize = L.k_size();
+    nd.gsize = L.g_size();
+    p->kparam_floats += nd.ksize;
     for (int k = 0; k < 4; ++k) nd.loss_w[k] = s.loss_w[k];
     nd.lr = s.lr;
     p->sd_poff[q + 1] = p->sd_poff[q] + nd.n_params;
@@ -216,9 +224,29 @@ int build_plan(ddp_problem* p) {
     p->ifaces.push_back(d);
   }
 
-  // work items per subdomain: residual, data and interface-side chunks
+  // Work items per subdomain: residual, data and interface-side chunks.  The
+  // chunk length of each network is chosen so items carry similar work
+  // (about 1/4 of an even share per workgroup), between one 64-point tile
+  // and chunk_max points: cheap networks get long items, expensive ones short.
+  double total_cost = 0.0;
+  for (int q = 0; q < n_sd; ++q) {
+    const HostSd& s = p->sds[q];
+    int n_pts = s.n_res + s.n_dat;
+    for (const HostIf& f : p->ifs)
+      if (f.a == q || f.b == q) n_pts += f.n;
+    total_cost += item_cost(p->nets[q], n_pts);
+  }
+  const double target = total_cost / (4.0 * std::max(1, p->plan_slots));
+  std::vector<int64_t> chunk_q(n_sd);
+  for (int q = 0; q < n_sd; ++q) {
+    const double per_pt = item_cost(p->nets[q], 1);
+    int64_t c = (int64_t)(target / per_pt);
+    c = (c + kTilePts - 1) / kTilePts * kTilePts;
+    chunk_q[q] = std::min(chunk_max, std::max<int64_t>(kTilePts, c));
+  }
   std::vector<std::vector<Item>> per_q(n_sd), vper_q(n_sd);
   auto add_chunks = [&](int q, int kind, int begin, int count, int iface, int side, float inv_n) {
+    const int64_t chunk = chunk_q[q];
     for (int64_t c0 = 0; c0 < count; c0 += chunk) {
       Item it{};
       it.q = q;
@@ -229,7 +257,20 @@ int build_plan(ddp_problem* p) {
       it.side = side;
       it.inv_n = inv_n;
       per_q[q].push_back(it);
-      if (kind == KIND_IFACE) vper_q[q].push_back(it);
+    }
+    if (kind == KIND_IFACE) {
+      // interface values: one tile per item (forward only, short)
+      for (int64_t c0 = 0; c0 < count; c0 += kTilePts) {
+        Item it{};
+        it.q = q;
+        it.kind = kind;
+        it.begin = begin + (int)c0;
+        it.count = (int)std::min<int64_t>(kTilePts, count - c0);
+        it.iface = iface;
+        it.side = side;
+        it.inv_n = inv_n;
+        vper_q[q].push_back(it);
+      }
     }
   };
   for (int q = 0; q < n_sd; ++q) {
@@ -269,7 +310,7 @@ int build_plan(ddp_problem* p) {
     Item& it = p->titems[i];
     it.lrow = i;
     it.prow = off;
-    off += p->nets[it.q].n_params;
+    off += p->nets[it.q].gsize;
   }
   p->partial_floats = off;
   // per subdomain row lists (ascending item index: a fixed summation order)
@@ -301,7 +342,7 @@ int build_plan(ddp_problem* p) {
 
 KArgs make_kargs(ddp_problem* p) {
   KArgs ka{};
-  ka.params = p->d_params;
+  ka.kparams = p->d_kparams;
   ka.nets = p->d_nets;
   ka.ifaces = p->d_ifaces;
   ka.res_xy = p->d_res_xy;
@@ -327,6 +368,7 @@ KArgs make_kargs(ddp_problem* p) {
 RArgs make_rargs(ddp_problem* p) {
   RArgs ra{};
   ra.params = p->d_params;
+  ra.kparams = p->d_kparams;
   ra.adam_m = p->d_m;
   ra.adam_v = p->d_v;
   ra.partial = p->d_partial;
@@ -563,7 +605,7 @@ int ddp_plan(ddp_problem* p) {
 int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   if (int rc = check_open(p)) return rc;
   p->fused = fused ? 1 : 0;
-  if (int rc = build_plan(p)) return rc;
+  if (int rc = build_plan(p)) return rc;  // provisional: fixes wpmax
   const int n_sd = (int)p->sds.size();
   HIP_TRY(hipGetDevice(&p->device));
   p->stream = static_cast<hipStream_t>(hip_stream);
@@ -574,6 +616,8 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   if (occ < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
   const int bpc = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, occ) : occ;
   p->n_slots = std::max(1, n_cu * bpc);
+  p->plan_slots = p->n_slots;
+  if (int rc = build_plan(p)) return rc;  // balanced for the resident workgroups
   p->slot_floats = scratch_slot_floats(p->wpmax);
   p->n_counters = n_sd + 1;
 
@@ -582,6 +626,7 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   if ((rc = dev_upload(p, &p->d_params, zeros))) return rc;
   if ((rc = dev_upload(p, &p->d_m, zeros))) return rc;
   if ((rc = dev_upload(p, &p->d_v, zeros))) return rc;
+  if ((rc = dev_upload(p, &p->d_kparams, std::vector<float>((size_t)p->kparam_floats, 0.f)))) return rc;
   if ((rc = dev_upload(p, &p->d_tstate, std::vector<int>{0, 0}))) return rc;
   if ((rc = dev_upload(p, &p->d_flags, std::vector<int>{0, 0}))) return rc;
   if ((rc = dev_upload(p, &p->d_counters, std::vector<int>(p->n_counters, 0)))) return rc;
@@ -641,6 +686,7 @@ int ddp_set_params(ddp_problem* p, int sd, const float* flat, int on_device) {
   const size_t n = (size_t)p->nets[sd].n_params;
   HIP_TRY(hipMemcpyAsync(p->d_params + p->sd_poff[sd], flat, n * sizeof(float),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(launch_pack(p->d_params, p->d_kparams, p->d_nets, p->d_sd_poff, sd, sd + 1, (int64_t)n, p->stream));
   if (!on_device) HIP_TRY(hipStreamSynchronize(p->stream));
   return DDP_OK;
 }
@@ -797,8 +843,11 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   std::fprintf(f, "\"nets\": [");
   for (size_t q = 0; q < p->nets.size(); ++q) {
     const NetDesc& n = p->nets[q];
-    std::fprintf(f, "%s{\"width\": %d, \"depth\": %d, \"d_out\": %d, \"wclass\": %d, \"poff\": %lld, \"n_params\": %d}",
-                 q ? ", " : "", n.width, n.depth, n.d_out, n.wclass, (long long)n.poff, n.n_params);
+    std::fprintf(f,
+                 "%s{\"width\": %d, \"depth\": %d, \"d_out\": %d, \"wclass\": %d, \"poff\": %lld, "
+                 "\"n_params\": %d, \"koff\": %lld, \"ksize\": %d, \"gsize\": %d}",
+                 q ? ", " : "", n.width, n.depth, n.d_out, n.wclass, (long long)n.poff, n.n_params, (long long)n.koff,
+                 n.ksize, n.gsize);
   }
   std::fprintf(f, "],\n\"ifaces\": [");
   for (size_t e = 0; e < p->ifaces.size(); ++e) {

@@ -19,6 +19,9 @@ hipError_t launch_values(int pde, int wpmax, const KArgs& ka, hipStream_t st);
 hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream_t st);
 // gradient reduction, loss reduction and optional Adam
 hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st);
+// refresh the kernel-layout parameter copy of subdomains [q_begin, q_end)
+hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets, const int64_t* sd_poff,
+                       int q_begin, int q_end, int64_t n, hipStream_t st);
 // stitched evaluation
 hipError_t launch_eval(const float* params, const NetDesc* nets, int n_sd, int n, const float* xy, const int* owner,
                        float* out, int d_out, hipStream_t st);

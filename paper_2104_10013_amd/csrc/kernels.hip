@@ -27,6 +27,9 @@
 // fixed order (deterministic, no float atomics) and applies Adam.
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+
 #include "ddp_internal.h"
 #include "kernels.h"
 
@@ -191,6 +194,23 @@ template <> struct Op<PDE_NS> {
 
 // ---------------------------------------------------------------------------
 // Tile processor for one padded width class WP.
+//
+// Lane layout (one wave = 16 points): lane = 16 g + pc holds point pc and,
+// for output block mb and register i, neuron 16 mb + 4 g + i.  This is the
+// C/D layout of v_mfma_f32_16x16x4_f32, and with the K index of the next
+// contraction permuted the same way it is also its B-operand layout.
+
+// one stream of the tanh rule (used when staging h^{k-1} for dW)
+template <bool S2>
+__device__ __forceinline__ float act_stream(int s, float a, float ax, float ay, float al) {
+  float t, s1;
+  tanh_s1(a, t, s1);
+  if (s == 0) return t;
+  if (s == 1) return s1 * ax;
+  if (s == 2) return s1 * ay;
+  const float q = S2 ? fmaf(ax, ax, ay * ay) : ax * ax;
+  return fmaf(s1, al, -2.f * t * s1 * q);
+}
 
 template <int WP, int PDE>
 struct Tile {
@@ -198,28 +218,24 @@ struct Tile {
   static constexpr int DO = Op<PDE>::DO;
   static constexpr int NEQ = Op<PDE>::NEQ;
   static constexpr bool S2 = Op<PDE>::S2;
-  static constexpr int WS = WP + 4;                         // LDS row stride of weights
-  static constexpr int NB = (MB * MB + kWaves - 1) / kWaves; // dW blocks per wave
-  static constexpr int KL = (DO * WP + NT - 1) / NT;         // output-layer slots per thread
+  static constexpr int WS = WP + 4;                         // row stride of staged weights
+  static constexpr int NBT = MB * MB;                       // 16x16 blocks of dW
+  static constexpr int NB = (NBT + kWaves - 1) / kWaves;    // dW blocks per wave
+  static constexpr int KL = (DO * WP + NT - 1) / NT;        // output-layer slots per thread
+  static constexpr int STASH_LAYER = kWaves * 4 * MB * 1024;  // bytes of one layer's stash
 
   typedef f4 Streams[4][MB];
 
   // layer 1: a = W^1 z + b^1, a_0 = W^1[:,0], a_1 = W^1[:,1], a_S = 0
-  __device__ static void layer1(const float* P, int w, float x, float y, int g, Streams& A) {
+  __device__ static void layer1(const float* K, float x, float y, int g, Streams& A) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int m = 16 * mb + 4 * g + i;
-        float w0 = 0.f, w1 = 0.f, b = 0.f;
-        if (m < w) {
-          w0 = P[2 * m];
-          w1 = P[2 * m + 1];
-          b = P[2 * w + m];
-        }
-        A[0][mb][i] = fmaf(w0, x, fmaf(w1, y, b));
-        A[1][mb][i] = w0;
-        A[2][mb][i] = w1;
+        const f4 c = *reinterpret_cast<const f4*>(K + (16 * mb + 4 * g + i) * 4);
+        A[0][mb][i] = fmaf(c[0], x, fmaf(c[1], y, c[2]));
+        A[1][mb][i] = c[0];
+        A[2][mb][i] = c[1];
         A[3][mb][i] = 0.f;
       }
     }
@@ -240,51 +256,26 @@ struct Tile {
     }
   }
 
-  // one stream of the activation (used when staging h^{k-1} for dW)
-  __device__ static void activate_stream(const Streams& A, int s, f4 (&Hs)[MB]) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float h, hx, hy, hl;
-        tanh_rule<S2>(A[0][mb][i], A[1][mb][i], A[2][mb][i], A[3][mb][i], h, hx, hy, hl);
-        Hs[mb][i] = s == 0 ? h : (s == 1 ? hx : (s == 2 ? hy : hl));
-      }
-    }
-  }
-
-  // W^k (w x w, row-major in global) -> LDS [m][j], zero padded to WP x WP
-  __device__ static void stage_w(float* sW, const float* Wg, int w) {
-    for (int idx = threadIdx.x; idx < WP * WP; idx += NT) {
-      const int m = idx / WP, j = idx - (idx / WP) * WP;
-      sW[m * WS + j] = (m < w && j < w) ? Wg[m * w + j] : 0.f;
-    }
-  }
-  // W^k transposed -> LDS [j][m]
-  __device__ static void stage_wt(float* sW, const float* Wg, int w) {
-    for (int idx = threadIdx.x; idx < WP * WP; idx += NT) {
-      const int m = idx / WP, j = idx - (idx / WP) * WP;
-      sW[j * WS + m] = (m < w && j < w) ? Wg[m * w + j] : 0.f;
-    }
+  // copy a zero-padded [WP][WS] matrix from the kernel layout into LDS
+  __device__ static void stage(float* sW, const float* src) {
+    constexpr int N4 = WP * WS / 4;
+    const f4* s4 = reinterpret_cast<const f4*>(src);
+    f4* d4 = reinterpret_cast<f4*>(sW);
+    for (int idx = threadIdx.x; idx < N4; idx += NT) d4[idx] = s4[idx];
   }
 
   // a^k = W^k h^{k-1} (+ b^k on the value stream), all four streams
-  __device__ static void hidden_fwd(const float* sW, const float* bias, int w, int g, int pc,
-                                    const Streams& H, Streams& A) {
+  __device__ static void hidden_fwd(const float* sW, const float* bias, int g, int pc, const Streams& H,
+                                    Streams& A) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int m = 16 * mb + 4 * g + i;
-        A[0][mb][i] = m < w ? bias[m] : 0.f;
-      }
+      A[0][mb] = *reinterpret_cast<const f4*>(bias + 16 * mb + 4 * g);
       A[1][mb] = f4{0.f, 0.f, 0.f, 0.f};
       A[2][mb] = f4{0.f, 0.f, 0.f, 0.f};
       A[3][mb] = f4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int kb = 0; kb < MB; ++kb) {
-      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const f4 wv = *reinterpret_cast<const f4*>(&sW[(16 * mb + pc) * WS + 16 * kb + 4 * g]);
@@ -297,13 +288,12 @@ struct Tile {
     }
   }
 
-  // g^{k-1}_s = W^{kT} abar^k_s for one stream s (sW holds W^T)
+  // g^{k-1}_s = W^{kT} abar^k_s for one stream (sW holds W^T)
   __device__ static void hidden_bwd_stream(const float* sWT, int g, int pc, const f4 (&Ab)[MB], f4 (&Gs)[MB]) {
 #pragma unroll
     for (int jb = 0; jb < MB; ++jb) Gs[jb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int jb = 0; jb < MB; ++jb) {
         const f4 wv = *reinterpret_cast<const f4*>(&sWT[(16 * jb + pc) * WS + 16 * mb + 4 * g]);
@@ -313,27 +303,38 @@ struct Tile {
     }
   }
 
-  // stash layout per workgroup slot: [layer k-2][wave][stream][mblock][lane] (float4)
-  __device__ static f4* stash_base(float* slot, int k, int wave, int lane) {
-    return reinterpret_cast<f4*>(slot) + (int64_t)(((k - 2) * kWaves + wave) * 4 * MB) * 64 + lane;
+  // stash of pre-activation streams, [layer k-2][wave][stream][mblock][lane] float4,
+  // addressed through a buffer resource over the workgroup's slot
+  __device__ static void stash_store(__amdgpu_buffer_rsrc_t rs, int k, int wave, int lane, const Streams& A) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        __builtin_amdgcn_raw_buffer_store_b128(A[s][mb], rs, lane * 16,
+                                               (k - 2) * STASH_LAYER + ((wave * 4 + s) * MB + mb) * 1024, 0);
+  }
+  __device__ static void stash_load(__amdgpu_buffer_rsrc_t rs, int k, int wave, int lane, Streams& A) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        A[s][mb] = __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16,
+                                                         (k - 2) * STASH_LAYER + ((wave * 4 + s) * MB + mb) * 1024, 0);
   }
 
   // output layer u = W^L h + b^L for DO outputs; every lane group ends with
   // the full sums for its point (bitwise identical across groups)
-  __device__ static void out_fwd(const float* WL, const float* bL, int w, int g, const Streams& H,
-                                 float (&u)[DO][4]) {
+  __device__ static void out_fwd(const float* WL, const float* bL, int g, const Streams& H, float (&u)[DO][4]) {
 #pragma unroll
     for (int c = 0; c < DO; ++c) {
       float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
+        const f4 wv = *reinterpret_cast<const f4*>(WL + c * WP + 16 * mb + 4 * g);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int j = 16 * mb + 4 * g + i;
-          const float wv = j < w ? WL[c * w + j] : 0.f;
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int s = 0; s < 4; ++s) acc[s] = fmaf(wv, H[s][mb][i], acc[s]);
-        }
+          for (int s = 0; s < 4; ++s) acc[s] = fmaf(wv[i], H[s][mb][i], acc[s]);
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -422,14 +423,20 @@ struct Tile {
     }
   }
 
+  __device__ static void accum(float* dst, float v, bool first) {
+    if (first) *dst = v;
+    else *dst += v;
+  }
+
   // ------------------------------------------------------------------------
   // forward only: interface values of this network (first kernel of a step)
   __device__ static void run_values(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds) {
     float* sW = lds;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, pc = lane & 15;
-    const int w = nd.width, D = nd.depth;
-    const float* P = ka.params + nd.poff;
+    const int D = nd.depth;
+    const Layout L(WP, D, DO);
+    const float* K = ka.kparams + nd.koff;
     const IfaceDesc ifd = ka.ifaces[it.iface];
     for (int t0 = 0; t0 < it.count; t0 += TP) {
       const int pt = t0 + wave * 16 + pc;
@@ -438,19 +445,17 @@ struct Tile {
       const float x = valid ? ka.if_xy[2 * (int64_t)gp] : 0.f;
       const float y = valid ? ka.if_xy[2 * (int64_t)gp + 1] : 0.f;
       Streams A, H;
-      layer1(P, w, x, y, g, A);
+      layer1(K, x, y, g, A);
       activate(A, H);
       for (int k = 2; k <= D; ++k) {
-        const int64_t off = 3 * w + (int64_t)(k - 2) * (w * w + w);
         __syncthreads();
-        stage_w(sW, P + off, w);
+        stage(sW, K + L.k_w(k));
         __syncthreads();
-        hidden_fwd(sW, P + off + w * w, w, g, pc, H, A);
+        hidden_fwd(sW, K + L.k_b(k), g, pc, H, A);
         activate(A, H);
       }
-      const int64_t offL = 3 * w + (int64_t)(D - 1) * (w * w + w);
       float u[DO][4];
-      out_fwd(P + offL, P + offL + DO * w, w, g, H, u);
+      out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
       if (valid && g == 0) {
         float ov[DO + NEQ];
         own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
@@ -474,11 +479,13 @@ struct Tile {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, pc = lane & 15;
     const int tp = wave * 16 + pc;
-    const int w = nd.width, D = nd.depth;
-    const float* P = ka.params + nd.poff;
+    const int D = nd.depth;
+    const Layout L(WP, D, DO);
+    const float* K = ka.kparams + nd.koff;
     float* R = ka.partial + it.prow;
     const float* xy = it.kind == KIND_RES ? ka.res_xy : (it.kind == KIND_DATA ? ka.dat_xy : ka.if_xy);
-    const int64_t offL = 3 * w + (int64_t)(D - 1) * (w * w + w);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(slot, 0, (int)(ka.scratch_slot * sizeof(float)), 0x00020000);
 
     for (int t0 = 0; t0 < it.count; t0 += TP) {
       const bool first = t0 == 0;
@@ -495,25 +502,18 @@ struct Tile {
 
       // ---- forward: Taylor streams through every layer, stash a^k
       Streams A, H;
-      layer1(P, w, x, y, g, A);
+      layer1(K, x, y, g, A);
       activate(A, H);
       for (int k = 2; k <= D; ++k) {
-        const int64_t off = 3 * w + (int64_t)(k - 2) * (w * w + w);
         __syncthreads();
-        stage_w(sW, P + off, w);
+        stage(sW, K + L.k_w(k));
         __syncthreads();
-        hidden_fwd(sW, P + off + w * w, w, g, pc, H, A);
-        {
-          f4* sb = stash_base(slot, k, wave, lane);
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) sb[(s * MB + mb) * 64] = A[s][mb];
-        }
+        hidden_fwd(sW, K + L.k_b(k), g, pc, H, A);
+        stash_store(rs, k, wave, lane, A);
         activate(A, H);
       }
       float u[DO][4];
-      out_fwd(P + offL, P + offL + DO * w, w, g, H, u);
+      out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
 
       // ---- loss terms and output seeds
       float ub[DO][4], loss[kLossTerms];
@@ -537,20 +537,19 @@ struct Tile {
       // ---- output layer adjoint: g^D = W^{LT} ubar; dW^L, db^L
       Streams G;
       {
-        const float* WL = P + offL;
+        const float* WL = K + L.k_out();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
+          f4 wl[DO];
+#pragma unroll
+          for (int c = 0; c < DO; ++c) wl[c] = *reinterpret_cast<const f4*>(WL + c * WP + 16 * mb + 4 * g);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int j = 16 * mb + 4 * g + i;
-            float wl[DO];
-#pragma unroll
-            for (int c = 0; c < DO; ++c) wl[c] = j < w ? WL[c * w + j] : 0.f;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
               float acc = 0.f;
 #pragma unroll
-              for (int c = 0; c < DO; ++c) acc = fmaf(wl[c], ub[c][s], acc);
+              for (int c = 0; c < DO; ++c) acc = fmaf(wl[c][i], ub[c][s], acc);
               G[s][mb][i] = acc;
             }
           }
@@ -581,38 +580,20 @@ struct Tile {
 #pragma unroll
       for (int r = 0; r < KL; ++r) {
         const int t = tid + r * NT;
-        if (t < DO * WP) {
-          const int c = t / WP, j = t - (t / WP) * WP;
-          if (j < w) {
-            float* dst = R + offL + c * w + j;
-            *dst = first ? accL[r] : *dst + accL[r];
-          }
-        }
+        if (t < DO * WP) accum(R + L.g_out() + t, accL[r], first);
       }
-      if (tid < DO) {
-        float* dst = R + offL + DO * w + tid;
-        *dst = first ? accB : *dst + accB;
-      }
+      if (tid < DO) accum(R + L.g_bout() + tid, accB, first);
       if (tid < kLossTerms) {
         float v = 0.f;
         for (int wv = 0; wv < kWaves; ++wv) v += sRed[wv * kLossTerms + tid];
-        v *= it.inv_n;
-        float* dst = ka.loss_part + (int64_t)it.lrow * kLossTerms + tid;
-        *dst = first ? v : *dst + v;
+        accum(ka.loss_part + (int64_t)it.lrow * kLossTerms + tid, v * it.inv_n, first);
       }
 
       // ---- hidden layers, top down
       if (D >= 2) {
         Streams Ak;
-        {
-          const f4* sb = stash_base(slot, D, wave, lane);
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) Ak[s][mb] = sb[(s * MB + mb) * 64];
-        }
+        stash_load(rs, D, wave, lane, Ak);
         for (int k = D; k >= 2; --k) {
-          const int64_t off = 3 * w + (int64_t)(k - 2) * (w * w + w);
           // abar^k from the stashed a^k and the incoming g^k
           Streams Ab;
 #pragma unroll
@@ -629,17 +610,10 @@ struct Tile {
             }
           }
           // a^{k-1}: stashed, or recomputed for layer 1
-          if (k - 1 >= 2) {
-            const f4* sb = stash_base(slot, k - 1, wave, lane);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-              for (int mb = 0; mb < MB; ++mb) Ak[s][mb] = sb[(s * MB + mb) * 64];
-          } else {
-            layer1(P, w, x, y, g, Ak);
-          }
+          if (k - 1 >= 2) stash_load(rs, k - 1, wave, lane, Ak);
+          else layer1(K, x, y, g, Ak);
           __syncthreads();
-          stage_wt(sW, P + off, w);
+          stage(sW, K + L.k_wt(k));
           // per stream: g^{k-1}_s = W^{kT} abar^k_s, then the stream's share of
           // dW^k = sum_{points, streams} abar^k h^{k-1 T}; db^k = sum_points abar^k_0
           f4 dacc[NB];
@@ -648,9 +622,6 @@ struct Tile {
           float dbias = 0.f;
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            __builtin_amdgcn_sched_barrier(0);
-            f4 Hs[MB];
-            activate_stream(Ak, s, Hs);
             __syncthreads();
             hidden_bwd_stream(sW, g, pc, Ab[s], G[s]);
 #pragma unroll
@@ -658,13 +629,14 @@ struct Tile {
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 sA[(16 * mb + 4 * g + i) * TPS + tp] = Ab[s][mb][i];
-                sH[(16 * mb + 4 * g + i) * TPS + tp] = Hs[mb][i];
+                sH[(16 * mb + 4 * g + i) * TPS + tp] =
+                    act_stream<S2>(s, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
               }
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < NB; ++r) {
               const int b = wave + r * kWaves;
-              if (b < MB * MB) {
+              if (b < NBT) {
                 const int mb = b / MB, jb = b - (b / MB) * MB;
 #pragma unroll
                 for (int gq = 0; gq < TP / 16; ++gq) {
@@ -677,34 +649,25 @@ struct Tile {
             }
             if (s == 0 && tid < WP) dbias = row_sum(sA + tid * TPS);
           }
+          float* Rw = R + L.g_w(k);
 #pragma unroll
           for (int r = 0; r < NB; ++r) {
             const int b = wave + r * kWaves;
-            if (b < MB * MB) {
+            if (b < NBT) {
               const int mb = b / MB, jb = b - (b / MB) * MB;
-              const int j = 16 * jb + pc;
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const int m = 16 * mb + 4 * g + i;
-                if (m < w && j < w) {
-                  float* dst = R + off + m * w + j;
-                  *dst = first ? dacc[r][i] : *dst + dacc[r][i];
-                }
-              }
+              for (int i = 0; i < 4; ++i) accum(Rw + (16 * mb + 4 * g + i) * WP + 16 * jb + pc, dacc[r][i], first);
             }
           }
-          if (tid < w) {
-            float* dst = R + off + w * w + tid;
-            *dst = first ? dbias : *dst + dbias;
-          }
+          if (tid < WP) accum(R + L.g_b(k) + tid, dbias, first);
         }
       }
 
       // ---- layer 1: abar^1 from a^1 and g^1; dW^1 and db^1 are sums over points
       {
         Streams A1;
-        layer1(P, w, x, y, g, A1);
-        Streams Ab;
+        layer1(K, x, y, g, A1);
+        __syncthreads();
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -712,19 +675,11 @@ struct Tile {
             float a0, a1, a2, a3;
             tanh_adj<S2>(A1[0][mb][i], A1[1][mb][i], A1[2][mb][i], A1[3][mb][i], G[0][mb][i], G[1][mb][i],
                          G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
-            Ab[0][mb][i] = a0;
-            Ab[1][mb][i] = a1;
-            Ab[2][mb][i] = a2;
+            sA[(16 * mb + 4 * g + i) * TPS + tp] = a0;
+            sH[(16 * mb + 4 * g + i) * TPS + tp] = a1;
+            G[2][mb][i] = a2;
           }
         }
-        __syncthreads();
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            sA[(16 * mb + 4 * g + i) * TPS + tp] = Ab[0][mb][i];
-            sH[(16 * mb + 4 * g + i) * TPS + tp] = Ab[1][mb][i];
-          }
         __syncthreads();
         float dw0 = 0.f, dw1 = 0.f, db = 0.f;
         if (tid < WP) {
@@ -735,16 +690,16 @@ struct Tile {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sH[(16 * mb + 4 * g + i) * TPS + tp] = Ab[2][mb][i];
+          for (int i = 0; i < 4; ++i) sH[(16 * mb + 4 * g + i) * TPS + tp] = G[2][mb][i];
         __syncthreads();
-        if (tid < WP) dw1 = row_dot_plus(sA + tid * TPS, sX + TP, sH + tid * TPS);
-        if (tid < w) {
-          float* d0 = R + 2 * tid;
-          float* d1 = R + 2 * tid + 1;
-          float* d2 = R + 2 * w + tid;
-          *d0 = first ? dw0 : *d0 + dw0;
-          *d1 = first ? dw1 : *d1 + dw1;
-          *d2 = first ? db : *d2 + db;
+        if (tid < WP) {
+          dw1 = row_dot_plus(sA + tid * TPS, sX + TP, sH + tid * TPS);
+          if (first) {
+            *reinterpret_cast<f4*>(R + 4 * tid) = f4{dw0, dw1, db, 0.f};
+          } else {
+            f4 o = *reinterpret_cast<f4*>(R + 4 * tid);
+            *reinterpret_cast<f4*>(R + 4 * tid) = f4{o[0] + dw0, o[1] + dw1, o[2] + db, 0.f};
+          }
         }
       }
     }
@@ -815,9 +770,61 @@ __global__ __launch_bounds__(NT) void k_train(KArgs ka) {
   }
 }
 
+// Position of canonical parameter li of a network in its gradient partial row
+// (g) and in its kernel-layout copy (k1, and k2 for the transposed copy of a
+// hidden weight, else -1).
+__device__ __forceinline__ void param_map(const NetDesc& nd, int li, int& g, int& k1, int& k2) {
+  const int w = nd.width, WP = nd.wclass, D = nd.depth, DO = nd.d_out;
+  const Layout L(WP, D, DO);
+  k2 = -1;
+  if (li < 2 * w) {                 // W^1[m][c]
+    const int m = li >> 1, c = li & 1;
+    g = k1 = m * 4 + c;
+    return;
+  }
+  if (li < 3 * w) {                 // b^1[m]
+    g = k1 = (li - 2 * w) * 4 + 2;
+    return;
+  }
+  int r = li - 3 * w;
+  const int per = w * w + w;
+  const int h = r / per;
+  if (h < D - 1) {                  // hidden layer k = h + 2
+    const int k = h + 2;
+    const int rr = r - h * per;
+    if (rr < w * w) {
+      const int m = rr / w, j = rr - (rr / w) * w;
+      g = L.g_w(k) + m * WP + j;
+      k1 = L.k_w(k) + m * L.WS + j;
+      k2 = L.k_wt(k) + j * L.WS + m;
+    } else {
+      const int m = rr - w * w;
+      g = L.g_b(k) + m;
+      k1 = L.k_b(k) + m;
+    }
+    return;
+  }
+  r -= (D - 1) * per;               // output layer
+  if (r < DO * w) {
+    const int c = r / w, j = r - (r / w) * w;
+    g = L.g_out() + c * WP + j;
+    k1 = L.k_out() + c * WP + j;
+  } else {
+    const int c = r - DO * w;
+    g = L.g_bout() + c;
+    k1 = L.k_bout() + c;
+  }
+}
+
+__device__ __forceinline__ int find_sd(const int64_t* sd_poff, int q, int64_t i) {
+  while (sd_poff[q + 1] <= i) ++q;
+  return q;
+}
+
 // Sum each subdomain's gradient partial rows in a fixed order, then write the
-// gradient and/or apply Adam (Kingma-Ba, bias corrected); block 0 also sums
-// the loss rows and flags non-finite losses.
+// gradient and/or apply Adam (Kingma-Ba, bias corrected) and refresh the
+// kernel-layout copy; block 0 also sums the loss rows and flags non-finite
+// losses.
 __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
   const int64_t p0 = ra.sd_poff[ra.q_begin], p1 = ra.sd_poff[ra.q_end];
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
@@ -826,11 +833,12 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
   const float bc2 = 1.f - powf(b2, tstep);
   for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1;
        i += (int64_t)gridDim.x * blockDim.x) {
-    int q = ra.q_begin;
-    while (ra.sd_poff[q + 1] <= i) ++q;
-    const int64_t li = i - ra.sd_poff[q];
+    const int q = find_sd(ra.sd_poff, ra.q_begin, i);
+    const NetDesc nd = ra.nets[q];
+    int gi, k1, k2;
+    param_map(nd, (int)(i - ra.sd_poff[q]), gi, k1, k2);
     float s = 0.f;
-    for (int r = ra.sd_row_ptr[q]; r < ra.sd_row_ptr[q + 1]; ++r) s += ra.partial[ra.row_prow[ra.sd_rows[r]] + li];
+    for (int r = ra.sd_row_ptr[q]; r < ra.sd_row_ptr[q + 1]; ++r) s += ra.partial[ra.row_prow[ra.sd_rows[r]] + gi];
     if (ra.grad_out) ra.grad_out[i] = s;
     if (ra.do_adam) {
       const float m = b1 * ra.adam_m[i] + (1.f - b1) * s;
@@ -839,7 +847,11 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
       ra.adam_v[i] = v;
       const float mh = m / bc1;
       const float vh = v / bc2;
-      ra.params[i] -= ra.nets[q].lr * mh / (sqrtf(vh) + eps);
+      const float th = ra.params[i] - nd.lr * mh / (sqrtf(vh) + eps);
+      ra.params[i] = th;
+      float* K = ra.kparams + nd.koff;
+      K[k1] = th;
+      if (k2 >= 0) K[k2] = th;
     }
   }
   if (blockIdx.x == 0) {
@@ -859,6 +871,23 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
       if (!isfinite(J)) ra.flags[0] = 1;
     }
     if (ra.do_adam && threadIdx.x == 0) ra.tstate[1] = 1;
+  }
+}
+
+// Rewrite the kernel-layout copy of subdomains [q_begin, q_end) from their
+// canonical parameters (after the caller sets them).
+__global__ __launch_bounds__(256) void k_pack(const float* params, float* kparams, const NetDesc* nets,
+                                              const int64_t* sd_poff, int q_begin, int q_end) {
+  const int64_t p0 = sd_poff[q_begin], p1 = sd_poff[q_end];
+  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int q = find_sd(sd_poff, q_begin, i);
+    const NetDesc nd = nets[q];
+    int gi, k1, k2;
+    param_map(nd, (int)(i - sd_poff[q]), gi, k1, k2);
+    float* K = kparams + nd.koff;
+    K[k1] = params[i];
+    if (k2 >= 0) K[k2] = params[i];
   }
 }
 
@@ -998,6 +1027,14 @@ hipError_t train_occupancy(int pde, int wpmax, int* blocks_per_cu) {
 
 hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, st, ra);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets, const int64_t* sd_poff,
+                       int q_begin, int q_end, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, params, kparams, nets, sd_poff, q_begin, q_end);
   return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ def test_plan_covers_every_point_once(name, tmp_path):
     # partial rows are disjoint and sized to the subdomain's parameters
     prow = items[:, 7]
     order = np.argsort(prow)
-    ends = prow[order] + np.array([nets[qq]["n_params"] for qq in q[order]])
+    ends = prow[order] + np.array([nets[qq]["gsize"] for qq in q[order]])
     assert (ends[:-1] <= prow[order][1:]).all() and ends[-1] == d["partial_floats"]
     # every item appears once in the per-subdomain row lists
     rows = np.array(d["sd_rows"])
