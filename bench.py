@@ -129,7 +129,7 @@ def main():
 
     pf, ms_fused = time_path(True)
     print(f"# fused: {ms_fused:.4f} ms/step", file=sys.stderr, flush=True)
-    kt = pf.time_kernels(max(10, min(args.steps, 100)))
+    kt = pf.time_kernels(max(10, min(args.steps, 50)))
     print(f"# kernels: {kt}", file=sys.stderr, flush=True)
     pf.close()
     plain = None

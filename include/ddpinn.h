@@ -64,7 +64,7 @@ enum { DDP_RESIDUAL = 0, DDP_DATA = 1 };
 
 /* tuning options (ddp_set_option), all optional */
 enum {
-  DDP_OPT_CHUNK_POINTS = 0, /* points per work item (multiple of the tile) */
+  DDP_OPT_CHUNK_POINTS = 0, /* upper bound of points per work item (default 1024) */
   DDP_OPT_BLOCKS_PER_CU = 1 /* persistent workgroups per compute unit (1 or 2) */
 };
 
@@ -139,10 +139,12 @@ int ddp_eval(ddp_problem* p, int n, const float* xy, const int* owner, float* u_
  * finite (the flag is then cleared). */
 int ddp_sync(ddp_problem* p);
 
-/* Average device time in milliseconds of each kernel of one fused step
- * (interface values, per-subdomain loss and gradient, reduction and Adam),
- * measured with HIP events over iters launches of each on the problem's
- * stream.  ms must hold 3 floats.  Leaves parameters unchanged. */
+/* Average device time in milliseconds, measured with HIP events on the
+ * problem's stream over iters repetitions: ms[0] = the train kernel launch(es)
+ * of one step (per-point loss, adjoint and gradient partials: one persistent
+ * launch when fused, one per subdomain otherwise), ms[1] = the reduction
+ * kernel (gradient and loss sums, without Adam).  ms must hold 2 floats.
+ * Leaves parameters and the Adam state unchanged. */
 int ddp_time_kernels(ddp_problem* p, int iters, float* ms);
 
 /* Write the packed plan (subdomains, interfaces, work items, offsets) as JSON.

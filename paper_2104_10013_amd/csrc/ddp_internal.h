@@ -90,20 +90,16 @@ struct KArgs {
   const float* dat_xy;
   const float* dat_g;     // d_out per point
   const float* if_xy;
-  float* if_val;          // per interface point: 2 sides x n_val
   float* partial;         // gradient partial rows
   float* loss_part;       // kLossTerms per loss row
   float* scratch;         // per-workgroup activation stash
   int64_t scratch_slot;   // floats per workgroup slot
-  int* counter;           // work counter of this launch
-  int* counters_all;      // all work counters (reset by the prologue)
-  int n_counters;
+  int* counter;           // work counter of this launch (zero at launch)
   int* tstate;            // [0] completed Adam steps, [1] pending increment
   int method;
   int n_eq;
-  int n_val;              // values per interface point and side
   float coef0;
-  int prologue;           // 1: this launch settles t and resets counters
+  int prologue;           // 1: block 0 settles the Adam step counter
 };
 
 // Arguments of the reduction / Adam kernel.
@@ -127,6 +123,7 @@ struct RArgs {
   int* flags;                 // [0] non-finite loss seen
   int* tstate;
   int do_adam;
+  int* counter_reset;         // work counter to re-arm for the next train launch
 };
 
 }  // namespace ddp

@@ -71,7 +71,7 @@ int width_class(int w) { return ((w + 15) / 16) * 16; }
 struct ddp_problem {
   int method = 0, pde = 0;
   double coef[4] = {0, 0, 0, 0};
-  int n_eq = 1, d_out = 1, n_val = 2;
+  int n_eq = 1, d_out = 1;
   std::vector<HostSd> sds;
   std::vector<HostIf> ifs;
   int64_t chunk_points = 1024;  // upper bound of points per work item
@@ -86,8 +86,7 @@ struct ddp_problem {
   int64_t kparam_floats = 0;
   int plan_slots = 512;          // workgroups the plan balances for
   std::vector<Item> titems;      // train items (fused: descending cost; plain: grouped by q)
-  std::vector<Item> vitems;      // interface-value items, grouped by q
-  std::vector<int> t_begin, v_begin;  // per q ranges (plain path), n_sd + 1
+  std::vector<int> t_begin;      // per q ranges (plain path), n_sd + 1
   std::vector<IfaceDesc> ifaces;
   std::vector<int> sd_rows, sd_row_ptr, row_lrow;
   std::vector<int64_t> row_prow;
@@ -104,10 +103,10 @@ struct ddp_problem {
   int *d_tstate = nullptr, *d_flags = nullptr, *d_counters = nullptr;
   int n_counters = 0;
   NetDesc* d_nets = nullptr;
-  Item *d_titems = nullptr, *d_vitems = nullptr;
+  Item* d_titems = nullptr;
   IfaceDesc* d_ifaces = nullptr;
   float *d_res_xy = nullptr, *d_res_f = nullptr, *d_dat_xy = nullptr, *d_dat_g = nullptr;
-  float *d_if_xy = nullptr, *d_if_val = nullptr;
+  float* d_if_xy = nullptr;
   float *d_partial = nullptr, *d_loss_part = nullptr, *d_scratch = nullptr, *d_loss = nullptr;
   int64_t* d_sd_poff = nullptr;
   int *d_sd_rows = nullptr, *d_sd_row_ptr = nullptr, *d_row_lrow = nullptr;
@@ -244,9 +243,11 @@ int build_plan(ddp_problem* p) {
     c = (c + kTilePts - 1) / kTilePts * kTilePts;
     chunk_q[q] = std::min(chunk_max, std::max<int64_t>(kTilePts, c));
   }
-  std::vector<std::vector<Item>> per_q(n_sd), vper_q(n_sd);
+  std::vector<std::vector<Item>> per_q(n_sd);
   auto add_chunks = [&](int q, int kind, int begin, int count, int iface, int side, float inv_n) {
-    const int64_t chunk = chunk_q[q];
+    // interface items are one tile: the neighbour's network is evaluated on
+    // the same tile first
+    const int64_t chunk = kind == KIND_IFACE ? kTilePts : chunk_q[q];
     for (int64_t c0 = 0; c0 < count; c0 += chunk) {
       Item it{};
       it.q = q;
@@ -257,20 +258,6 @@ int build_plan(ddp_problem* p) {
       it.side = side;
       it.inv_n = inv_n;
       per_q[q].push_back(it);
-    }
-    if (kind == KIND_IFACE) {
-      // interface values: one tile per item (forward only, short)
-      for (int64_t c0 = 0; c0 < count; c0 += kTilePts) {
-        Item it{};
-        it.q = q;
-        it.kind = kind;
-        it.begin = begin + (int)c0;
-        it.count = (int)std::min<int64_t>(kTilePts, count - c0);
-        it.iface = iface;
-        it.side = side;
-        it.inv_n = inv_n;
-        vper_q[q].push_back(it);
-      }
     }
   };
   for (int q = 0; q < n_sd; ++q) {
@@ -328,14 +315,6 @@ int build_plan(ddp_problem* p) {
     p->row_prow[i] = p->titems[i].prow;
     p->row_lrow[i] = p->titems[i].lrow;
   }
-  // interface-value items grouped by subdomain
-  p->vitems.clear();
-  p->v_begin.assign(n_sd + 1, 0);
-  for (int q = 0; q < n_sd; ++q) {
-    p->v_begin[q] = (int)p->vitems.size();
-    p->vitems.insert(p->vitems.end(), vper_q[q].begin(), vper_q[q].end());
-  }
-  p->v_begin[n_sd] = (int)p->vitems.size();
   p->planned = true;
   return DDP_OK;
 }
@@ -350,17 +329,13 @@ KArgs make_kargs(ddp_problem* p) {
   ka.dat_xy = p->d_dat_xy;
   ka.dat_g = p->d_dat_g;
   ka.if_xy = p->d_if_xy;
-  ka.if_val = p->d_if_val;
   ka.partial = p->d_partial;
   ka.loss_part = p->d_loss_part;
   ka.scratch = p->d_scratch;
   ka.scratch_slot = p->slot_floats;
-  ka.counters_all = p->d_counters;
-  ka.n_counters = p->n_counters;
   ka.tstate = p->d_tstate;
   ka.method = p->method;
   ka.n_eq = p->n_eq;
-  ka.n_val = p->n_val;
   ka.coef0 = (float)p->coef[0];
   return ka;
 }
@@ -395,14 +370,10 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
   const int n_sd = (int)p->sds.size();
   if (p->fused) {
     KArgs ka = make_kargs(p);
-    ka.items = p->d_vitems;
-    ka.n_items = (int)p->vitems.size();
-    ka.prologue = 1;
-    HIP_TRY(launch_values(p->pde, p->wpmax, ka, st));
-    ka = make_kargs(p);
     ka.items = p->d_titems;
     ka.n_items = (int)p->titems.size();
     ka.counter = p->d_counters;
+    ka.prologue = 1;
     const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
     HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, st));
     RArgs ra = make_rargs(p);
@@ -411,23 +382,19 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     ra.grad_out = grad_out;
     ra.loss_out = loss_out;
     ra.do_adam = do_adam;
+    ra.counter_reset = p->d_counters;
     HIP_TRY(launch_reduce(ra, reduce_grid(p, 0, n_sd), st));
     return DDP_OK;
   }
-  // plain path: the same kernels, one launch set per subdomain
-  for (int q = 0; q < n_sd; ++q) {
-    KArgs ka = make_kargs(p);
-    ka.items = p->d_vitems + p->v_begin[q];
-    ka.n_items = p->v_begin[q + 1] - p->v_begin[q];
-    ka.prologue = q == 0;
-    if (ka.n_items > 0 || q == 0) HIP_TRY(launch_values(p->pde, p->wpmax, ka, st));
-  }
+  // plain path: the same kernels, one launch pair per subdomain; every
+  // subdomain's loss and gradient use the parameters from before the step
   for (int q = 0; q < n_sd; ++q) {
     KArgs ka = make_kargs(p);
     ka.items = p->d_titems + p->t_begin[q];
     ka.n_items = p->t_begin[q + 1] - p->t_begin[q];
     ka.counter = p->d_counters + 1 + q;
-    if (ka.n_items == 0) continue;
+    ka.prologue = q == 0;
+    if (ka.n_items == 0 && q != 0) continue;
     const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
     HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, st));
   }
@@ -438,6 +405,7 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     ra.grad_out = grad_out;
     ra.loss_out = loss_out;
     ra.do_adam = do_adam;
+    ra.counter_reset = p->d_counters + 1 + q;
     HIP_TRY(launch_reduce(ra, reduce_grid(p, q, q + 1), st));
   }
   return DDP_OK;
@@ -500,7 +468,6 @@ int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n
   for (int i = 0; i < n_coef; ++i) p->coef[i] = coef[i];
   p->d_out = pde == DDP_NS2D_STEADY ? 3 : 1;
   p->n_eq = pde == DDP_NS2D_STEADY ? 3 : 1;
-  p->n_val = p->d_out + p->n_eq;
   *out = p;
   return DDP_OK;
 }
@@ -632,14 +599,12 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   if ((rc = dev_upload(p, &p->d_counters, std::vector<int>(p->n_counters, 0)))) return rc;
   if ((rc = dev_upload(p, &p->d_nets, p->nets))) return rc;
   if ((rc = dev_upload(p, &p->d_titems, p->titems))) return rc;
-  if ((rc = dev_upload(p, &p->d_vitems, p->vitems))) return rc;
   if ((rc = dev_upload(p, &p->d_ifaces, p->ifaces))) return rc;
   if ((rc = dev_upload(p, &p->d_res_xy, p->h_res_xy))) return rc;
   if ((rc = dev_upload(p, &p->d_res_f, p->h_res_f))) return rc;
   if ((rc = dev_upload(p, &p->d_dat_xy, p->h_dat_xy))) return rc;
   if ((rc = dev_upload(p, &p->d_dat_g, p->h_dat_g))) return rc;
   if ((rc = dev_upload(p, &p->d_if_xy, p->h_if_xy))) return rc;
-  if ((rc = dev_upload(p, &p->d_if_val, std::vector<float>(p->h_if_xy.size() / 2 * 2 * p->n_val, 0.f)))) return rc;
   if ((rc = dev_alloc(p, &p->d_partial, (size_t)p->partial_floats))) return rc;
   if ((rc = dev_alloc(p, &p->d_loss_part, p->titems.size() * kLossTerms))) return rc;
   if ((rc = dev_alloc(p, &p->d_scratch, (size_t)p->n_slots * p->slot_floats))) return rc;
@@ -775,42 +740,22 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
   hipEvent_t ev[2];
   HIP_TRY(hipEventCreate(&ev[0]));
   HIP_TRY(hipEventCreate(&ev[1]));
-  for (int which = 0; which < 3; ++which) {
+  // [0]: every train launch of one step, [1]: reduction without Adam
+  for (int which = 0; which < 2; ++which) {
     float total = 0.f;
     for (int i = 0; i < iters; ++i) {
-      if (which == 1) {
-        // clear the work counters outside the timed window
-        KArgs kz = make_kargs(p);
-        kz.items = p->d_vitems;
-        kz.n_items = 0;
-        kz.prologue = 1;
-        HIP_TRY(launch_values(p->pde, p->wpmax, kz, p->stream));
-      }
+      if (which == 0)
+        for (int c = 0; c <= n_sd; ++c) HIP_TRY(launch_reset_counter(p->d_counters + c, p->stream));
       HIP_TRY(hipEventRecord(ev[0], p->stream));
       if (which == 0) {
-        KArgs ka = make_kargs(p);
-        ka.items = p->d_vitems;
-        ka.n_items = (int)p->vitems.size();
-        ka.prologue = 1;
-        HIP_TRY(launch_values(p->pde, p->wpmax, ka, p->stream));
-      } else if (which == 1) {
-        if (p->fused) {
+        for (int q = 0; q < (p->fused ? 1 : n_sd); ++q) {
           KArgs ka = make_kargs(p);
-          ka.items = p->d_titems;
-          ka.n_items = (int)p->titems.size();
-          ka.counter = p->d_counters;
+          ka.items = p->d_titems + (p->fused ? 0 : p->t_begin[q]);
+          ka.n_items = p->fused ? (int)p->titems.size() : p->t_begin[q + 1] - p->t_begin[q];
+          ka.counter = p->d_counters + (p->fused ? 0 : 1 + q);
+          if (ka.n_items == 0) continue;
           const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
           HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, p->stream));
-        } else {
-          for (int q = 0; q < n_sd; ++q) {
-            KArgs ka = make_kargs(p);
-            ka.items = p->d_titems + p->t_begin[q];
-            ka.n_items = p->t_begin[q + 1] - p->t_begin[q];
-            ka.counter = p->d_counters + 1 + q;
-            if (ka.n_items == 0) continue;
-            const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
-            HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, p->stream));
-          }
         }
       } else {
         RArgs ra = make_rargs(p);
@@ -828,6 +773,7 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
     }
     ms[which] = total / iters;
   }
+  for (int c = 0; c <= n_sd; ++c) HIP_TRY(launch_reset_counter(p->d_counters + c, p->stream));
   hipEventDestroy(ev[0]);
   hipEventDestroy(ev[1]);
   return DDP_OK;
@@ -864,7 +810,6 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
     }
   };
   items("train_items", p->titems);
-  items("value_items", p->vitems);
   std::fprintf(f, "],\n");
   json_ints(f, "sd_row_ptr", p->sd_row_ptr);
   std::fprintf(f, ",\n");

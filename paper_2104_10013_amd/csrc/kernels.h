@@ -5,19 +5,19 @@
 
 namespace ddp {
 
-// dynamic LDS bytes of the values (train = false) or train kernel for a width class
-size_t lds_bytes(int pde, int wpmax, bool train);
+// dynamic LDS bytes of the train kernel for a width class
+size_t lds_bytes(int pde, int wpmax);
 // floats of one workgroup's activation stash for the widest class wpmax
 int64_t scratch_slot_floats(int wpmax);
 // resident train workgroups per compute unit (also raises the LDS limit)
 hipError_t train_occupancy(int pde, int wpmax, int* blocks_per_cu);
 
-// interface values: one workgroup per item; ka.prologue settles Adam's t and
-// clears the work counters
-hipError_t launch_values(int pde, int wpmax, const KArgs& ka, hipStream_t st);
-// persistent loss + gradient-partial kernel over ka.items
+// persistent loss + gradient-partial kernel over ka.items (ka.prologue:
+// settle the Adam step counter first)
 hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream_t st);
-// gradient reduction, loss reduction and optional Adam
+// set a work counter to zero
+hipError_t launch_reset_counter(int* c, hipStream_t st);
+// gradient reduction, loss reduction and optional Adam; re-arms ra.counter_reset
 hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st);
 // refresh the kernel-layout parameter copy of subdomains [q_begin, q_end)
 hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets, const int64_t* sd_poff,

@@ -368,7 +368,8 @@ struct Tile {
   // loss contributions and output seeds of one point (the derivative of the
   // item's share of J_q with respect to the output streams)
   __device__ static void epilogue(const KArgs& ka, const Item& it, const NetDesc& nd, int pt, bool valid,
-                                  const float (&u)[DO][4], float (&ub)[DO][4], float (&loss)[kLossTerms]) {
+                                  const float* nb, const float (&u)[DO][4], float (&ub)[DO][4],
+                                  float (&loss)[kLossTerms]) {
 #pragma unroll
     for (int c = 0; c < DO; ++c)
 #pragma unroll
@@ -399,7 +400,6 @@ struct Tile {
       const IfaceDesc ifd = ka.ifaces[it.iface];
       float ov[DO + NEQ];
       own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
-      const float* nb = ka.if_val + ((int64_t)gp * 2 + (1 - it.side)) * ka.n_val;
 #pragma unroll
       for (int c = 0; c < DO; ++c) {
         const float d = ov[c] - nb[c];
@@ -429,46 +429,45 @@ struct Tile {
   }
 
   // ------------------------------------------------------------------------
-  // forward only: interface values of this network (first kernel of a step)
-  __device__ static void run_values(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds) {
+  // forward only: the values this network contributes on the interface points
+  // of a one-tile item (u and flux.n or L_x(u)), written to LDS for the other
+  // side's loss -- the exchange of Algorithm 1 as an on-chip read
+  __device__ static void values_tile(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* sNb) {
     float* sW = lds;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, pc = lane & 15;
-    const int D = nd.depth;
-    const Layout L(WP, D, DO);
+    const int tp = wave * 16 + pc;
+    const Layout L(WP, nd.depth, DO);
     const float* K = ka.kparams + nd.koff;
     const IfaceDesc ifd = ka.ifaces[it.iface];
-    for (int t0 = 0; t0 < it.count; t0 += TP) {
-      const int pt = t0 + wave * 16 + pc;
-      const bool valid = pt < it.count;
-      const int gp = it.begin + pt;
-      const float x = valid ? ka.if_xy[2 * (int64_t)gp] : 0.f;
-      const float y = valid ? ka.if_xy[2 * (int64_t)gp + 1] : 0.f;
-      Streams A, H;
-      layer1(K, x, y, g, A);
+    const bool valid = tp < it.count;
+    const int gp = it.begin + tp;
+    const float x = valid ? ka.if_xy[2 * (int64_t)gp] : 0.f;
+    const float y = valid ? ka.if_xy[2 * (int64_t)gp + 1] : 0.f;
+    Streams A, H;
+    layer1(K, x, y, g, A);
+    activate(A, H);
+    for (int k = 2; k <= nd.depth; ++k) {
+      __syncthreads();
+      stage(sW, K + L.k_w(k));
+      __syncthreads();
+      hidden_fwd(sW, K + L.k_b(k), g, pc, H, A);
       activate(A, H);
-      for (int k = 2; k <= D; ++k) {
-        __syncthreads();
-        stage(sW, K + L.k_w(k));
-        __syncthreads();
-        hidden_fwd(sW, K + L.k_b(k), g, pc, H, A);
-        activate(A, H);
-      }
-      float u[DO][4];
-      out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
-      if (valid && g == 0) {
-        float ov[DO + NEQ];
-        own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
-        float* dst = ka.if_val + ((int64_t)gp * 2 + it.side) * ka.n_val;
-        for (int v = 0; v < ka.n_val; ++v) dst[v] = ov[v];
-      }
+    }
+    float u[DO][4];
+    out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
+    if (g == 0) {
+      float ov[DO + NEQ];
+      own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
+#pragma unroll
+      for (int v = 0; v < DO + NEQ; ++v) sNb[tp * (DO + NEQ) + v] = ov[v];
     }
   }
 
   // ------------------------------------------------------------------------
   // forward, loss, adjoint and parameter-gradient partials of one item
   __device__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
-                                   float* slot) {
+                                   float* slot, const float* sNb) {
     float* sW = lds;
     float* sA = sW + WP * WS;
     float* sH = sA + WP * TPS;
@@ -517,7 +516,7 @@ struct Tile {
 
       // ---- loss terms and output seeds
       float ub[DO][4], loss[kLossTerms];
-      epilogue(ka, it, nd, pt, valid, u, ub, loss);
+      epilogue(ka, it, nd, pt, valid, sNb + tp * (DO + NEQ), u, ub, loss);
 #pragma unroll
       for (int t = 0; t < kLossTerms; ++t) {
         float v = g == 0 ? loss[t] : 0.f;
@@ -708,47 +707,40 @@ struct Tile {
 
 template <int WP, int PDE>
 constexpr int lds_train_floats() {
-  return WP * (WP + 4) + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms;
+  return WP * (WP + 4) + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms + 6 * TP;
 }
 
-template <int WPMAX, int PDE, bool TRAIN>
+// Run one item: for an interface item first evaluate the neighbour's network
+// on the same tile (its width class may differ), then the item's own network.
+template <int WPMAX, int PDE>
 __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                          float* slot) {
-#define DDP_CASE(WPV)                                                          \
-  case WPV:                                                                    \
-    if constexpr (WPV <= WPMAX) {                                              \
-      if constexpr (TRAIN) Tile<WPV, PDE>::run_train(ka, it, nd, lds, slot);   \
-      else Tile<WPV, PDE>::run_values(ka, it, nd, lds);                        \
-    }                                                                          \
+  float* sNb = lds + lds_train_floats<WPMAX, PDE>() - 6 * TP;
+#define DDP_CASE(WPV, CALL)                            \
+  case WPV:                                            \
+    if constexpr (WPV <= WPMAX) Tile<WPV, PDE>::CALL;  \
     break;
-  switch (nd.wclass) {
-    DDP_CASE(16)
-    DDP_CASE(32)
-    DDP_CASE(48)
-    DDP_CASE(64)
-    DDP_CASE(80)
-    DDP_CASE(96)
-    DDP_CASE(112)
-    default: break;
+#define DDP_SWITCH(CLS, CALL) \
+  switch (CLS) {              \
+    DDP_CASE(16, CALL)        \
+    DDP_CASE(32, CALL)        \
+    DDP_CASE(48, CALL)        \
+    DDP_CASE(64, CALL)        \
+    DDP_CASE(80, CALL)        \
+    DDP_CASE(96, CALL)        \
+    DDP_CASE(112, CALL)       \
+    default: break;           \
   }
+  if (it.kind == KIND_IFACE) {
+    const IfaceDesc ifd = ka.ifaces[it.iface];
+    const NetDesc ndn = ka.nets[it.side == 0 ? ifd.b : ifd.a];
+    __syncthreads();
+    DDP_SWITCH(ndn.wclass, values_tile(ka, it, ndn, lds, sNb))
+    __syncthreads();
+  }
+  DDP_SWITCH(nd.wclass, run_train(ka, it, nd, lds, slot, sNb))
+#undef DDP_SWITCH
 #undef DDP_CASE
-}
-
-// First kernel of a step: interface values of every network (the exchange of
-// Algorithm 1 becomes this kernel's output buffer); block 0 also settles the
-// Adam step counter and clears the work counters.
-template <int WPMAX, int PDE>
-__global__ __launch_bounds__(NT) void k_values(KArgs ka) {
-  extern __shared__ float lds[];
-  if (ka.prologue && blockIdx.x == 0 && threadIdx.x == 0) {
-    ka.tstate[0] += ka.tstate[1];
-    ka.tstate[1] = 0;
-    for (int i = 0; i < ka.n_counters; ++i) ka.counters_all[i] = 0;
-  }
-  if ((int)blockIdx.x >= ka.n_items) return;
-  const Item it = ka.items[blockIdx.x];
-  const NetDesc nd = ka.nets[it.q];
-  dispatch<WPMAX, PDE, false>(ka, it, nd, lds, nullptr);
 }
 
 // Persistent kernel: workgroups pull items (in descending cost order) from a
@@ -758,6 +750,11 @@ __global__ __launch_bounds__(NT) void k_train(KArgs ka) {
   extern __shared__ float lds[];
   __shared__ int s_item;
   float* slot = ka.scratch + (int64_t)blockIdx.x * ka.scratch_slot;
+  if (ka.prologue && blockIdx.x == 0 && threadIdx.x == 0) {
+    // settle the Adam step counter of the previous update (k_reduce reads it)
+    ka.tstate[0] += ka.tstate[1];
+    ka.tstate[1] = 0;
+  }
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(ka.counter, 1);
     __syncthreads();
@@ -766,7 +763,7 @@ __global__ __launch_bounds__(NT) void k_train(KArgs ka) {
     if (idx >= ka.n_items) break;
     const Item it = ka.items[idx];
     const NetDesc nd = ka.nets[it.q];
-    dispatch<WPMAX, PDE, true>(ka, it, nd, lds, slot);
+    dispatch<WPMAX, PDE>(ka, it, nd, lds, slot);
   }
 }
 
@@ -871,8 +868,12 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
       if (!isfinite(J)) ra.flags[0] = 1;
     }
     if (ra.do_adam && threadIdx.x == 0) ra.tstate[1] = 1;
+    // the train kernel of this step has finished: re-arm its work counter
+    if (ra.counter_reset && threadIdx.x == 0) *ra.counter_reset = 0;
   }
 }
+
+__global__ void k_reset_counter(int* c) { *c = 0; }
 
 // Rewrite the kernel-layout copy of subdomains [q_begin, q_end) from their
 // canonical parameters (after the caller sets them).
@@ -946,15 +947,10 @@ static int wclass_index(int wpmax) {
 
 template <int PDE>
 struct KTable {
-  static const void* values[7];
   static const void* train[7];
   static int lds[7];
 };
 #define DDP_ROW(PDE)                                                                            \
-  template <> const void* KTable<PDE>::values[7] = {                                            \
-      (const void*)k_values<16, PDE>, (const void*)k_values<32, PDE>, (const void*)k_values<48, PDE>, \
-      (const void*)k_values<64, PDE>, (const void*)k_values<80, PDE>, (const void*)k_values<96, PDE>, \
-      (const void*)k_values<112, PDE>};                                                         \
   template <> const void* KTable<PDE>::train[7] = {                                             \
       (const void*)k_train<16, PDE>, (const void*)k_train<32, PDE>, (const void*)k_train<48, PDE>, \
       (const void*)k_train<64, PDE>, (const void*)k_train<80, PDE>, (const void*)k_train<96, PDE>, \
@@ -968,21 +964,20 @@ DDP_ROW(PDE_BURGERS)
 DDP_ROW(PDE_NS)
 #undef DDP_ROW
 
-static const void* pick(int pde, int wpmax, bool train) {
+static const void* pick(int pde, int wpmax) {
   const int c = wclass_index(wpmax);
   if (c < 0) return nullptr;
   switch (pde) {
-    case PDE_POISSON: return train ? KTable<PDE_POISSON>::train[c] : KTable<PDE_POISSON>::values[c];
-    case PDE_BURGERS: return train ? KTable<PDE_BURGERS>::train[c] : KTable<PDE_BURGERS>::values[c];
-    case PDE_NS: return train ? KTable<PDE_NS>::train[c] : KTable<PDE_NS>::values[c];
+    case PDE_POISSON: return KTable<PDE_POISSON>::train[c];
+    case PDE_BURGERS: return KTable<PDE_BURGERS>::train[c];
+    case PDE_NS: return KTable<PDE_NS>::train[c];
   }
   return nullptr;
 }
 
-size_t lds_bytes(int pde, int wpmax, bool train) {
+size_t lds_bytes(int pde, int wpmax) {
   const int c = wclass_index(wpmax);
   if (c < 0) return 0;
-  if (!train) return (size_t)wpmax * (wpmax + 4) * sizeof(float);
   int f = 0;
   switch (pde) {
     case PDE_POISSON: f = KTable<PDE_POISSON>::lds[c]; break;
@@ -996,33 +991,26 @@ int64_t scratch_slot_floats(int wpmax) {
   return (int64_t)(kMaxDepth - 1) * kWaves * 4 * (wpmax / 16) * 64 * 4;
 }
 
-hipError_t launch_values(int pde, int wpmax, const KArgs& ka, hipStream_t st) {
-  const void* fn = pick(pde, wpmax, false);
-  if (!fn) return hipErrorInvalidValue;
-  KArgs a = ka;
-  void* args[] = {&a};
-  const int grid = ka.n_items > 0 ? ka.n_items : 1;
-  return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds_bytes(pde, wpmax, false), st);
-}
-
 hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream_t st) {
-  const void* fn = pick(pde, wpmax, true);
+  const void* fn = pick(pde, wpmax);
   if (!fn) return hipErrorInvalidValue;
   KArgs a = ka;
   void* args[] = {&a};
-  return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds_bytes(pde, wpmax, true), st);
+  return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds_bytes(pde, wpmax), st);
 }
 
 hipError_t train_occupancy(int pde, int wpmax, int* blocks_per_cu) {
-  const void* fn = pick(pde, wpmax, true);
+  const void* fn = pick(pde, wpmax);
   if (!fn) return hipErrorInvalidValue;
-  const size_t lds = lds_bytes(pde, wpmax, true);
+  const size_t lds = lds_bytes(pde, wpmax);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(pick(pde, wpmax, false), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds_bytes(pde, wpmax, false));
-  if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, NT, lds);
+}
+
+hipError_t launch_reset_counter(int* c, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, c);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st) {
