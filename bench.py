@@ -98,6 +98,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--chunk-points", type=int, default=None)
+    ap.add_argument("--kernel-only", type=int, default=0, metavar="N",
+                    help="profiling mode: set up the fused step, then launch only the train kernel N times")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="profiling mode: copy a float32 buffer of MIB MiB 5 times (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
@@ -107,7 +111,24 @@ def main():
     import torch
     from paper_2104_10013_amd import ddpinn, workloads as W
 
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}))
+        return
+
     prob = W.make_problem(WORKLOAD, seed=args.seed)
+    if args.kernel_only:
+        pb = ddpinn.Problem(prob, fused=True, device="cuda:0", chunk_points=args.chunk_points)
+        pb.step(2)
+        kt = pb.time_kernels(args.kernel_only)
+        pb.close()
+        print(json.dumps({"kernel_only": args.kernel_only, "kernel_ms": kt}))
+        return
     n_res = prob.n_residual()
     flops = algorithmic_flops(prob)
     dev = torch.device("cuda:0")

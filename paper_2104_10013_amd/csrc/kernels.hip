@@ -41,6 +41,15 @@ constexpr int TP = kTilePts;      // points per tile
 constexpr int TPS = kTilePts + 4; // LDS row stride of staged tiles (floats)
 constexpr int NT = 64 * kWaves;   // threads per workgroup
 
+// Per-item copy of the thread index the compiler cannot treat as loop
+// invariant: keeps per-lane address arithmetic of every width class from being
+// hoisted out of the persistent item loop (where it would pin registers).
+__device__ __forceinline__ int item_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -257,11 +266,11 @@ struct Tile {
   }
 
   // copy a zero-padded [WP][WS] matrix from the kernel layout into LDS
-  __device__ static void stage(float* sW, const float* src) {
+  __device__ static void stage(float* sW, const float* src, int tid) {
     constexpr int N4 = WP * WS / 4;
     const f4* s4 = reinterpret_cast<const f4*>(src);
     f4* d4 = reinterpret_cast<f4*>(sW);
-    for (int idx = threadIdx.x; idx < N4; idx += NT) d4[idx] = s4[idx];
+    for (int idx = tid; idx < N4; idx += NT) d4[idx] = s4[idx];
   }
 
   // a^k = W^k h^{k-1} (+ b^k on the value stream), all four streams
@@ -276,6 +285,7 @@ struct Tile {
     }
 #pragma unroll
     for (int kb = 0; kb < MB; ++kb) {
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const f4 wv = *reinterpret_cast<const f4*>(&sW[(16 * mb + pc) * WS + 16 * kb + 4 * g]);
@@ -294,6 +304,7 @@ struct Tile {
     for (int jb = 0; jb < MB; ++jb) Gs[jb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int jb = 0; jb < MB; ++jb) {
         const f4 wv = *reinterpret_cast<const f4*>(&sWT[(16 * jb + pc) * WS + 16 * mb + 4 * g]);
@@ -303,23 +314,35 @@ struct Tile {
     }
   }
 
-  // stash of pre-activation streams, [layer k-2][wave][stream][mblock][lane] float4,
-  // addressed through a buffer resource over the workgroup's slot
-  __device__ static void stash_store(__amdgpu_buffer_rsrc_t rs, int k, int wave, int lane, const Streams& A) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
-        __builtin_amdgcn_raw_buffer_store_b128(A[s][mb], rs, lane * 16,
-                                               (k - 2) * STASH_LAYER + ((wave * 4 + s) * MB + mb) * 1024, 0);
+  // Activation stash of the workgroup's slot, [region][layer][wave][stream][mblock][lane]
+  // float4, addressed through a buffer resource: region 0 holds the
+  // pre-activation streams a^k (k = 2..D), region 1 the post-activation
+  // streams h^k (k = 1..D-1) the reverse pass needs for dW^{k+1}.
+  static constexpr int STASH_REGION = (kMaxDepth - 1) * STASH_LAYER;
+  __device__ static int stash_off(int region, int layer, int wave, int s, int mb) {
+    return region * STASH_REGION + layer * STASH_LAYER + ((wave * 4 + s) * MB + mb) * 1024;
   }
-  __device__ static void stash_load(__amdgpu_buffer_rsrc_t rs, int k, int wave, int lane, Streams& A) {
+  __device__ static void stash_store(__amdgpu_buffer_rsrc_t rs, int region, int layer, int wave, int lane,
+                                     const Streams& A) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
-        A[s][mb] = __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16,
-                                                         (k - 2) * STASH_LAYER + ((wave * 4 + s) * MB + mb) * 1024, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(A[s][mb], rs, lane * 16, stash_off(region, layer, wave, s, mb), 0);
+  }
+  __device__ static void stash_load(__amdgpu_buffer_rsrc_t rs, int region, int layer, int wave, int lane,
+                                    Streams& A) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        A[s][mb] = __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, stash_off(region, layer, wave, s, mb), 0);
+  }
+  __device__ static void stash_load_stream(__amdgpu_buffer_rsrc_t rs, int region, int layer, int wave, int lane,
+                                           int s, f4 (&As)[MB]) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      As[mb] = __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, stash_off(region, layer, wave, s, mb), 0);
   }
 
   // output layer u = W^L h + b^L for DO outputs; every lane group ends with
@@ -434,7 +457,8 @@ struct Tile {
   // side's loss -- the exchange of Algorithm 1 as an on-chip read
   __device__ static void values_tile(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* sNb) {
     float* sW = lds;
-    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = item_tid();
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, pc = lane & 15;
     const int tp = wave * 16 + pc;
     const Layout L(WP, nd.depth, DO);
@@ -449,7 +473,7 @@ struct Tile {
     activate(A, H);
     for (int k = 2; k <= nd.depth; ++k) {
       __syncthreads();
-      stage(sW, K + L.k_w(k));
+      stage(sW, K + L.k_w(k), tid);
       __syncthreads();
       hidden_fwd(sW, K + L.k_b(k), g, pc, H, A);
       activate(A, H);
@@ -474,7 +498,7 @@ struct Tile {
     float* sU = sH + WP * TPS;       // [4 streams][3 outputs][TP]
     float* sX = sU + 4 * 3 * TP;     // [2][TP]
     float* sRed = sX + 2 * TP;       // [kWaves][kLossTerms]
-    const int tid = threadIdx.x;
+    const int tid = item_tid();
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, pc = lane & 15;
     const int tp = wave * 16 + pc;
@@ -504,11 +528,12 @@ struct Tile {
       layer1(K, x, y, g, A);
       activate(A, H);
       for (int k = 2; k <= D; ++k) {
+        stash_store(rs, 1, k - 2, wave, lane, H);   // h^{k-1}
         __syncthreads();
-        stage(sW, K + L.k_w(k));
+        stage(sW, K + L.k_w(k), tid);
         __syncthreads();
         hidden_fwd(sW, K + L.k_b(k), g, pc, H, A);
-        stash_store(rs, k, wave, lane, A);
+        stash_store(rs, 0, k - 2, wave, lane, A);   // a^k
         activate(A, H);
       }
       float u[DO][4];
@@ -589,77 +614,81 @@ struct Tile {
       }
 
       // ---- hidden layers, top down
-      if (D >= 2) {
-        Streams Ak;
-        stash_load(rs, D, wave, lane, Ak);
-        for (int k = D; k >= 2; --k) {
-          // abar^k from the stashed a^k and the incoming g^k
-          Streams Ab;
+      for (int k = D; k >= 2; --k) {
+        // abar^k from the stashed a^k and the incoming g^k (in place of g^k)
+        {
+          Streams Ak;
+          stash_load(rs, 0, k - 2, wave, lane, Ak);
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               float a0, a1, a2, a3;
-              tanh_adj<S2>(Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i], G[0][mb][i],
-                           G[1][mb][i], G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
-              Ab[0][mb][i] = a0;
-              Ab[1][mb][i] = a1;
-              Ab[2][mb][i] = a2;
-              Ab[3][mb][i] = a3;
+              tanh_adj<S2>(Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i], G[0][mb][i], G[1][mb][i],
+                           G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
+              G[0][mb][i] = a0;
+              G[1][mb][i] = a1;
+              G[2][mb][i] = a2;
+              G[3][mb][i] = a3;
             }
           }
-          // a^{k-1}: stashed, or recomputed for layer 1
-          if (k - 1 >= 2) stash_load(rs, k - 1, wave, lane, Ak);
-          else layer1(K, x, y, g, Ak);
+        }
+        Streams& Ab = G;
+        __syncthreads();
+        stage(sW, K + L.k_wt(k), tid);
+        // per stream: g^{k-1}_s = W^{kT} abar^k_s, then the stream's share of
+        // dW^k = sum_{points, streams} abar^k h^{k-1 T}; db^k = sum_points abar^k_0
+        f4 dacc[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) dacc[r] = f4{0.f, 0.f, 0.f, 0.f};
+        float dbias = 0.f;
+        Streams Gn;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          f4 Hs[MB];
+          stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s
           __syncthreads();
-          stage(sW, K + L.k_wt(k));
-          // per stream: g^{k-1}_s = W^{kT} abar^k_s, then the stream's share of
-          // dW^k = sum_{points, streams} abar^k h^{k-1 T}; db^k = sum_points abar^k_0
-          f4 dacc[NB];
+          hidden_bwd_stream(sW, g, pc, Ab[s], Gn[s]);
 #pragma unroll
-          for (int r = 0; r < NB; ++r) dacc[r] = f4{0.f, 0.f, 0.f, 0.f};
-          float dbias = 0.f;
+          for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            __syncthreads();
-            hidden_bwd_stream(sW, g, pc, Ab[s], G[s]);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                sA[(16 * mb + 4 * g + i) * TPS + tp] = Ab[s][mb][i];
-                sH[(16 * mb + 4 * g + i) * TPS + tp] =
-                    act_stream<S2>(s, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
-              }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < NB; ++r) {
-              const int b = wave + r * kWaves;
-              if (b < NBT) {
-                const int mb = b / MB, jb = b - (b / MB) * MB;
-#pragma unroll
-                for (int gq = 0; gq < TP / 16; ++gq) {
-                  const f4 av = *reinterpret_cast<const f4*>(&sA[(16 * mb + pc) * TPS + 16 * gq + 4 * g]);
-                  const f4 hv = *reinterpret_cast<const f4*>(&sH[(16 * jb + pc) * TPS + 16 * gq + 4 * g]);
-#pragma unroll
-                  for (int i = 0; i < 4; ++i) dacc[r] = mma(av[i], hv[i], dacc[r]);
-                }
-              }
+            for (int i = 0; i < 4; ++i) {
+              sA[(16 * mb + 4 * g + i) * TPS + tp] = Ab[s][mb][i];
+              sH[(16 * mb + 4 * g + i) * TPS + tp] = Hs[mb][i];
             }
-            if (s == 0 && tid < WP) dbias = row_sum(sA + tid * TPS);
-          }
-          float* Rw = R + L.g_w(k);
+          __syncthreads();
 #pragma unroll
           for (int r = 0; r < NB; ++r) {
+            __builtin_amdgcn_sched_barrier(0);
             const int b = wave + r * kWaves;
             if (b < NBT) {
               const int mb = b / MB, jb = b - (b / MB) * MB;
 #pragma unroll
-              for (int i = 0; i < 4; ++i) accum(Rw + (16 * mb + 4 * g + i) * WP + 16 * jb + pc, dacc[r][i], first);
+              for (int gq = 0; gq < TP / 16; ++gq) {
+                const f4 av = *reinterpret_cast<const f4*>(&sA[(16 * mb + pc) * TPS + 16 * gq + 4 * g]);
+                const f4 hv = *reinterpret_cast<const f4*>(&sH[(16 * jb + pc) * TPS + 16 * gq + 4 * g]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dacc[r] = mma(av[i], hv[i], dacc[r]);
+              }
             }
           }
-          if (tid < WP) accum(R + L.g_b(k) + tid, dbias, first);
+          if (s == 0 && tid < WP) dbias = row_sum(sA + tid * TPS);
         }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) G[s][mb] = Gn[s][mb];
+        float* Rw = R + L.g_w(k);
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          const int b = wave + r * kWaves;
+          if (b < NBT) {
+            const int mb = b / MB, jb = b - (b / MB) * MB;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) accum(Rw + (16 * mb + 4 * g + i) * WP + 16 * jb + pc, dacc[r][i], first);
+          }
+        }
+        if (tid < WP) accum(R + L.g_b(k) + tid, dbias, first);
       }
 
       // ---- layer 1: abar^1 from a^1 and g^1; dW^1 and db^1 are sums over points
@@ -988,7 +1017,8 @@ size_t lds_bytes(int pde, int wpmax) {
 }
 
 int64_t scratch_slot_floats(int wpmax) {
-  return (int64_t)(kMaxDepth - 1) * kWaves * 4 * (wpmax / 16) * 64 * 4;
+  // two regions (a^k and h^k) of kMaxDepth - 1 layers
+  return (int64_t)2 * (kMaxDepth - 1) * kWaves * 4 * (wpmax / 16) * 64 * 4;
 }
 
 hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream_t st) {

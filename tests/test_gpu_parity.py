@@ -227,3 +227,40 @@ def test_autograd_function_backward():
     ref = torch.cat([g[pb.offsets[q]:pb.offsets[q + 1]] * w[q] for q in range(4)])
     assert torch.equal(flat.grad, ref)
     pb.close()
+
+
+@pytest.mark.parametrize("name", ["c3_cpinn_burgers", "c4_xpinn_kovasznay", "c1_cpinn_poisson"])
+def test_full_size_configs_at_init(name):
+    """Every workload at its full size, fused launch, initial parameters."""
+    prob = W.make_problem(name, seed=0)
+    params = _params(prob, None)
+    _say(f"{name} full size")
+    pb, lt, g = run(prob, params)
+    wl, wg = compare(prob, params, lt, g)
+    _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+    pb.close()
+
+
+def test_c4_adjoint_vs_central_fd_of_oracle_loss():
+    """The GPU gradient of a Navier-Stokes subdomain loss against central
+    differences (h = 1e-3, FP64) of the oracle's J_q on sampled parameters."""
+    prob = W.c4_xpinn_kovasznay(seed=0, scale=0.02)
+    params = _params(prob, 5)
+    _say("c4 adjoint vs central FD")
+    pb, lt, g = run(prob, params)
+    rng = np.random.default_rng(0)
+    for q in (0, 4):
+        idx = rng.choice(len(params[q]), 12, replace=False)
+        base = [torch.tensor(p, dtype=torch.float64) for p in params]
+        for i in idx:
+            h = 1e-3
+            bp = [b.clone() for b in base]
+            bm = [b.clone() for b in base]
+            bp[q][i] += h
+            bm[q][i] -= h
+            jp = float(oracle.subdomain_terms(prob, q, bp)[0].detach())
+            jm = float(oracle.subdomain_terms(prob, q, bm)[0].detach())
+            fd = (jp - jm) / (2 * h)
+            scale = np.linalg.norm(g[q]) / np.sqrt(len(g[q]))
+            assert abs(g[q][i] - fd) <= 1e-3 * max(abs(fd), scale), (q, i, g[q][i], fd)
+    pb.close()
