@@ -65,7 +65,8 @@ enum { DDP_RESIDUAL = 0, DDP_DATA = 1 };
 /* tuning options (ddp_set_option), all optional */
 enum {
   DDP_OPT_CHUNK_POINTS = 0, /* upper bound of points per work item (default 1024) */
-  DDP_OPT_BLOCKS_PER_CU = 1 /* persistent workgroups per compute unit (1 or 2) */
+  DDP_OPT_BLOCKS_PER_CU = 1, /* persistent workgroups per compute unit (0 = as many as fit) */
+  DDP_OPT_ITEMS_PER_SLOT = 2 /* work items per resident workgroup the plan aims for (default 4) */
 };
 
 /* Create an empty problem.  coef holds n_coef operator constants (see the
@@ -104,6 +105,17 @@ int ddp_set_option(ddp_problem* p, int option, int64_t value);
  * without the persistent schedule or a graph.  Parameters start at zero;
  * set them with ddp_set_params.  Topology calls fail with DDP_ESTATE after. */
 int ddp_finalize(ddp_problem* p, void* hip_stream, int fused);
+
+/* Autotuner: time candidate work plans on this problem (points per item
+ * bound, items per resident workgroup, workgroups per compute unit) with
+ * iters loss-and-gradient passes each, keep the fastest and rebuild the step
+ * graph with it.  Parameters and Adam state are not changed.  cache_path (may
+ * be NULL) is a JSON-lines file of earlier choices keyed by a signature of the
+ * problem (operator, method, widths, depths, point counts, CU count): a hit
+ * skips the search, a miss appends the new choice.  choice (may be NULL)
+ * receives the 3 chosen values.  Not safe to call while the caller's stream
+ * runs other work on this problem. */
+int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* choice);
 
 /* Number of parameters of subdomain sd's network (canonical layout). */
 int ddp_param_count(const ddp_problem* p, int sd, int64_t* n);

@@ -75,7 +75,8 @@ struct ddp_problem {
   std::vector<HostSd> sds;
   std::vector<HostIf> ifs;
   int64_t chunk_points = 1024;  // upper bound of points per work item
-  int blocks_per_cu = 0;  // 0: from the occupancy query
+  int blocks_per_cu = 0;         // 0: from the occupancy query
+  int items_per_slot = 4;        // work items per resident workgroup the plan aims for
 
   // plan
   bool planned = false, finalized = false;
@@ -113,7 +114,9 @@ struct ddp_problem {
   int64_t* d_row_prow = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  std::vector<void*> allocations;
+  std::vector<void*> allocations;       // static buffers
+  std::vector<void*> plan_allocations;  // buffers that depend on the work plan
+  int n_cu = 0, occupancy = 0;
 };
 
 namespace {
@@ -127,6 +130,23 @@ int dev_alloc(ddp_problem* p, T** out, size_t count) {
   if (e != hipSuccess) return fail(DDP_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   p->allocations.push_back(ptr);
   *out = static_cast<T*>(ptr);
+  return DDP_OK;
+}
+
+template <class T>
+int plan_alloc(ddp_problem* p, T** out, size_t count) {
+  int rc = dev_alloc(p, out, count);
+  if (rc) return rc;
+  p->allocations.pop_back();
+  p->plan_allocations.push_back(*out);
+  return DDP_OK;
+}
+
+template <class T>
+int plan_upload(ddp_problem* p, T** out, const std::vector<T>& v) {
+  int rc = plan_alloc(p, out, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIP_TRY(hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return DDP_OK;
 }
 
@@ -235,7 +255,7 @@ int build_plan(ddp_problem* p) {
       if (f.a == q || f.b == q) n_pts += f.n;
     total_cost += item_cost(p->nets[q], n_pts);
   }
-  const double target = total_cost / (4.0 * std::max(1, p->plan_slots));
+  const double target = total_cost / ((double)std::max(1, p->items_per_slot) * std::max(1, p->plan_slots));
   std::vector<int64_t> chunk_q(n_sd);
   for (int q = 0; q < n_sd; ++q) {
     const double per_pt = item_cost(p->nets[q], 1);
@@ -418,6 +438,8 @@ void release(ddp_problem* p) {
   p->graph = nullptr;
   for (void* a : p->allocations) hipFree(a);
   p->allocations.clear();
+  for (void* a : p->plan_allocations) hipFree(a);
+  p->plan_allocations.clear();
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   p->cap_stream = nullptr;
 }
@@ -557,6 +579,10 @@ int ddp_set_option(ddp_problem* p, int option, int64_t value) {
       if (value < 0 || value > 8) return fail(DDP_EINVAL, "blocks per CU out of range");
       p->blocks_per_cu = (int)value;
       break;
+    case DDP_OPT_ITEMS_PER_SLOT:
+      if (value < 1 || value > 64) return fail(DDP_EINVAL, "items per slot out of range");
+      p->items_per_slot = (int)value;
+      break;
     default:
       return fail(DDP_EINVAL, "unknown option");
   }
@@ -569,59 +595,45 @@ int ddp_plan(ddp_problem* p) {
   return build_plan(p);
 }
 
-int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
-  if (int rc = check_open(p)) return rc;
-  p->fused = fused ? 1 : 0;
-  if (int rc = build_plan(p)) return rc;  // provisional: fixes wpmax
+}  // extern "C"
+
+namespace {
+
+// Build the work plan for the current options and (re)create everything that
+// depends on it: work items, gradient / loss partial rows, row lists, the
+// activation stash, work counters and the step graph.
+int install_plan(ddp_problem* p) {
   const int n_sd = (int)p->sds.size();
-  HIP_TRY(hipGetDevice(&p->device));
-  p->stream = static_cast<hipStream_t>(hip_stream);
-  int n_cu = 0;
-  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
-  int occ = 0;
-  HIP_TRY(train_occupancy(p->pde, p->wpmax, &occ));
-  if (occ < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
-  const int bpc = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, occ) : occ;
-  p->n_slots = std::max(1, n_cu * bpc);
+  if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  if (p->stream) HIP_TRY(hipStreamSynchronize(p->stream));
+  for (void* a : p->plan_allocations) hipFree(a);
+  p->plan_allocations.clear();
+  const int bpc = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, p->occupancy) : p->occupancy;
+  p->n_slots = std::max(1, p->n_cu * bpc);
   p->plan_slots = p->n_slots;
-  if (int rc = build_plan(p)) return rc;  // balanced for the resident workgroups
+  if (int rc = build_plan(p)) return rc;
   p->slot_floats = scratch_slot_floats(p->wpmax);
   p->n_counters = n_sd + 1;
-
   int rc = 0;
-  std::vector<float> zeros(p->sd_poff[n_sd], 0.f);
-  if ((rc = dev_upload(p, &p->d_params, zeros))) return rc;
-  if ((rc = dev_upload(p, &p->d_m, zeros))) return rc;
-  if ((rc = dev_upload(p, &p->d_v, zeros))) return rc;
-  if ((rc = dev_upload(p, &p->d_kparams, std::vector<float>((size_t)p->kparam_floats, 0.f)))) return rc;
-  if ((rc = dev_upload(p, &p->d_tstate, std::vector<int>{0, 0}))) return rc;
-  if ((rc = dev_upload(p, &p->d_flags, std::vector<int>{0, 0}))) return rc;
-  if ((rc = dev_upload(p, &p->d_counters, std::vector<int>(p->n_counters, 0)))) return rc;
-  if ((rc = dev_upload(p, &p->d_nets, p->nets))) return rc;
-  if ((rc = dev_upload(p, &p->d_titems, p->titems))) return rc;
-  if ((rc = dev_upload(p, &p->d_ifaces, p->ifaces))) return rc;
-  if ((rc = dev_upload(p, &p->d_res_xy, p->h_res_xy))) return rc;
-  if ((rc = dev_upload(p, &p->d_res_f, p->h_res_f))) return rc;
-  if ((rc = dev_upload(p, &p->d_dat_xy, p->h_dat_xy))) return rc;
-  if ((rc = dev_upload(p, &p->d_dat_g, p->h_dat_g))) return rc;
-  if ((rc = dev_upload(p, &p->d_if_xy, p->h_if_xy))) return rc;
-  if ((rc = dev_alloc(p, &p->d_partial, (size_t)p->partial_floats))) return rc;
-  if ((rc = dev_alloc(p, &p->d_loss_part, p->titems.size() * kLossTerms))) return rc;
-  if ((rc = dev_alloc(p, &p->d_scratch, (size_t)p->n_slots * p->slot_floats))) return rc;
-  if ((rc = dev_alloc(p, &p->d_loss, (size_t)n_sd * 5))) return rc;
-  if ((rc = dev_upload(p, &p->d_sd_poff, p->sd_poff))) return rc;
-  if ((rc = dev_upload(p, &p->d_sd_rows, p->sd_rows))) return rc;
-  if ((rc = dev_upload(p, &p->d_sd_row_ptr, p->sd_row_ptr))) return rc;
-  if ((rc = dev_upload(p, &p->d_row_prow, p->row_prow))) return rc;
-  if ((rc = dev_upload(p, &p->d_row_lrow, p->row_lrow))) return rc;
+  if ((rc = plan_upload(p, &p->d_counters, std::vector<int>(p->n_counters, 0)))) return rc;
+  if ((rc = plan_upload(p, &p->d_titems, p->titems))) return rc;
+  if ((rc = plan_alloc(p, &p->d_partial, (size_t)p->partial_floats))) return rc;
+  if ((rc = plan_alloc(p, &p->d_loss_part, p->titems.size() * kLossTerms))) return rc;
+  if ((rc = plan_alloc(p, &p->d_scratch, (size_t)p->n_slots * p->slot_floats))) return rc;
+  if ((rc = plan_upload(p, &p->d_sd_rows, p->sd_rows))) return rc;
+  if ((rc = plan_upload(p, &p->d_sd_row_ptr, p->sd_row_ptr))) return rc;
+  if ((rc = plan_upload(p, &p->d_row_prow, p->row_prow))) return rc;
+  if ((rc = plan_upload(p, &p->d_row_lrow, p->row_lrow))) return rc;
   HIP_TRY(hipMemset(p->d_partial, 0, (size_t)std::max<int64_t>(1, p->partial_floats) * sizeof(float)));
   HIP_TRY(hipMemset(p->d_loss_part, 0, std::max<size_t>(1, p->titems.size() * kLossTerms) * sizeof(float)));
   HIP_TRY(hipDeviceSynchronize());
-
   if (p->fused) {
     // one training step as a graph: captured on a private stream, replayed on
     // the caller's stream
-    HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     rc = enqueue_step(p, p->cap_stream, 1, nullptr, p->d_loss);
     hipGraph_t g = nullptr;
@@ -634,7 +646,157 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
     p->graph = g;
     HIP_TRY(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
   }
+  return DDP_OK;
+}
+
+// FNV-1a hash of everything the best plan depends on
+uint64_t problem_signature(const ddp_problem* p) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(p->pde);
+  mix(p->method);
+  mix(p->n_cu);
+  mix((int64_t)p->sds.size());
+  for (const HostSd& s : p->sds) {
+    for (int w : s.widths) mix(w);
+    mix(s.n_res);
+    mix(s.n_dat);
+  }
+  for (const HostIf& f : p->ifs) {
+    mix(f.a);
+    mix(f.b);
+    mix(f.n);
+  }
+  return h;
+}
+
+bool cache_lookup(const char* path, uint64_t sig, int64_t* cfg) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    unsigned long long s = 0;
+    long long c = 0, ips = 0, bpc = 0;
+    if (std::sscanf(line, "{\"signature\": \"%llx\", \"chunk_points\": %lld, \"items_per_slot\": %lld, "
+                          "\"blocks_per_cu\": %lld",
+                    &s, &c, &ips, &bpc) == 4 &&
+        s == sig) {
+      cfg[0] = c;
+      cfg[1] = ips;
+      cfg[2] = bpc;
+      found = true;  // the last entry for a signature wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
+  if (int rc = check_open(p)) return rc;
+  p->fused = fused ? 1 : 0;
+  if (int rc = build_plan(p)) return rc;  // validates and fixes wpmax
+  const int n_sd = (int)p->sds.size();
+  HIP_TRY(hipGetDevice(&p->device));
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  HIP_TRY(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
+  HIP_TRY(train_occupancy(p->pde, p->wpmax, &p->occupancy));
+  if (p->occupancy < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
+
+  int rc = 0;
+  std::vector<float> zeros(p->sd_poff[n_sd], 0.f);
+  if ((rc = dev_upload(p, &p->d_params, zeros))) return rc;
+  if ((rc = dev_upload(p, &p->d_m, zeros))) return rc;
+  if ((rc = dev_upload(p, &p->d_v, zeros))) return rc;
+  if ((rc = dev_upload(p, &p->d_kparams, std::vector<float>((size_t)p->kparam_floats, 0.f)))) return rc;
+  if ((rc = dev_upload(p, &p->d_tstate, std::vector<int>{0, 0}))) return rc;
+  if ((rc = dev_upload(p, &p->d_flags, std::vector<int>{0, 0}))) return rc;
+  if ((rc = dev_upload(p, &p->d_nets, p->nets))) return rc;
+  if ((rc = dev_upload(p, &p->d_ifaces, p->ifaces))) return rc;
+  if ((rc = dev_upload(p, &p->d_res_xy, p->h_res_xy))) return rc;
+  if ((rc = dev_upload(p, &p->d_res_f, p->h_res_f))) return rc;
+  if ((rc = dev_upload(p, &p->d_dat_xy, p->h_dat_xy))) return rc;
+  if ((rc = dev_upload(p, &p->d_dat_g, p->h_dat_g))) return rc;
+  if ((rc = dev_upload(p, &p->d_if_xy, p->h_if_xy))) return rc;
+  if ((rc = dev_alloc(p, &p->d_loss, (size_t)n_sd * 5))) return rc;
+  if ((rc = dev_upload(p, &p->d_sd_poff, p->sd_poff))) return rc;
+  if ((rc = install_plan(p))) return rc;
   p->finalized = true;
+  return DDP_OK;
+}
+
+int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* choice) {
+  if (int rc = check_final(p)) return rc;
+  if (iters < 1) return fail(DDP_EINVAL, "iters must be >= 1");
+  const uint64_t sig = problem_signature(p);
+  int64_t best[3] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu};
+  if (!cache_lookup(cache_path, sig, best)) {
+    const int n_sd = (int)p->sds.size();
+    float best_ms = 1e30f;
+    hipEvent_t ev[2];
+    HIP_TRY(hipEventCreate(&ev[0]));
+    HIP_TRY(hipEventCreate(&ev[1]));
+    const int64_t chunks[] = {512, 1024, 2048};
+    const int ipss[] = {2, 4, 8};
+    for (int64_t c : chunks) {
+      for (int ips : ipss) {
+        for (int bpc = 1; bpc <= p->occupancy; ++bpc) {
+          p->chunk_points = c;
+          p->items_per_slot = ips;
+          p->blocks_per_cu = bpc;
+          if (int rc = install_plan(p)) return rc;
+          // one untimed pass, then the timed passes (loss + gradient, no Adam)
+          if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
+          HIP_TRY(hipEventRecord(ev[0], p->stream));
+          for (int i = 0; i < iters; ++i)
+            if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
+          HIP_TRY(hipEventRecord(ev[1], p->stream));
+          HIP_TRY(hipEventSynchronize(ev[1]));
+          float ms = 0.f;
+          HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+          ms /= iters;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best[0] = c;
+            best[1] = ips;
+            best[2] = bpc;
+          }
+        }
+      }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    (void)n_sd;
+    if (cache_path) {
+      FILE* f = std::fopen(cache_path, "a");
+      if (f) {
+        std::fprintf(f,
+                     "{\"signature\": \"%016llx\", \"chunk_points\": %lld, \"items_per_slot\": %lld, "
+                     "\"blocks_per_cu\": %lld, \"ms\": %.5f}\n",
+                     (unsigned long long)sig, (long long)best[0], (long long)best[1], (long long)best[2], best_ms);
+        std::fclose(f);
+      }
+    }
+  }
+  p->chunk_points = best[0];
+  p->items_per_slot = (int)best[1];
+  p->blocks_per_cu = (int)best[2];
+  if (int rc = install_plan(p)) return rc;
+  if (choice) {
+    choice[0] = best[0];
+    choice[1] = best[1];
+    choice[2] = best[2];
+  }
   return DDP_OK;
 }
 

@@ -21,13 +21,13 @@ DDP_OK, DDP_EINVAL, DDP_ENOMEM, DDP_EHIP, DDP_ESTATE, DDP_ENONFINITE = 0, -1, -2
 DDP_CPINN, DDP_XPINN = 0, 1
 DDP_POISSON2D, DDP_BURGERS1D, DDP_NS2D_STEADY = 0, 1, 2
 DDP_RESIDUAL, DDP_DATA = 0, 1
-DDP_OPT_CHUNK_POINTS, DDP_OPT_BLOCKS_PER_CU = 0, 1
+DDP_OPT_CHUNK_POINTS, DDP_OPT_BLOCKS_PER_CU, DDP_OPT_ITEMS_PER_SLOT = 0, 1, 2
 
 EXPORTED = [
     "ddp_create", "ddp_add_subdomain", "ddp_set_points", "ddp_add_interface", "ddp_set_option",
     "ddp_finalize", "ddp_param_count", "ddp_set_params", "ddp_get_params", "ddp_loss_and_grad",
     "ddp_step", "ddp_get_state", "ddp_set_state", "ddp_eval", "ddp_sync", "ddp_time_kernels",
-    "ddp_plan_dump", "ddp_plan", "ddp_last_error", "ddp_destroy",
+    "ddp_plan_dump", "ddp_plan", "ddp_last_error", "ddp_destroy", "ddp_autotune",
 ]
 
 _METHOD = {W.METHOD_CPINN: DDP_CPINN, W.METHOD_XPINN: DDP_XPINN}
@@ -73,6 +73,7 @@ def load_library(path=LIB_PATH):
         "ddp_plan": ([P], I),
         "ddp_last_error": ([], ctypes.c_char_p),
         "ddp_destroy": ([P], I),
+        "ddp_autotune": ([P, I, ctypes.c_char_p, pI64], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -106,7 +107,7 @@ class Problem:
     HIP graph.  fused=False: the same kernels launched per subdomain."""
 
     def __init__(self, prob: W.Problem, fused=True, device="cuda", stream=None, chunk_points=None,
-                 blocks_per_cu=None, plan_only=False):
+                 blocks_per_cu=None, items_per_slot=None, plan_only=False):
         L = load_library()
         self.prob = prob
         self.fused = bool(fused)
@@ -134,6 +135,8 @@ class Problem:
                 _check(L.ddp_set_option(self._h, DDP_OPT_CHUNK_POINTS, int(chunk_points)))
             if blocks_per_cu is not None:
                 _check(L.ddp_set_option(self._h, DDP_OPT_BLOCKS_PER_CU, int(blocks_per_cu)))
+            if items_per_slot is not None:
+                _check(L.ddp_set_option(self._h, DDP_OPT_ITEMS_PER_SLOT, int(items_per_slot)))
             self.n_params = []
             for q in range(self.n_sd):
                 n = ctypes.c_int64()
@@ -223,6 +226,13 @@ class Problem:
         ms = (ctypes.c_float * 2)()
         _check(_lib.ddp_time_kernels(self._h, int(iters), ms))
         return {"train_ms": ms[0], "reduce_ms": ms[1]}
+
+    def autotune(self, iters=5, cache_path=None):
+        """Pick the fastest work plan (see ddp_autotune); returns the choice."""
+        ch = (ctypes.c_int64 * 3)()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(_lib.ddp_autotune(self._h, int(iters), path, ch))
+        return {"chunk_points": ch[0], "items_per_slot": ch[1], "blocks_per_cu": ch[2]}
 
     def plan_dump(self, path):
         _check(_lib.ddp_plan_dump(self._h, str(path).encode()))

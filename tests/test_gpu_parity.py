@@ -264,3 +264,23 @@ def test_c4_adjoint_vs_central_fd_of_oracle_loss():
             scale = np.linalg.norm(g[q]) / np.sqrt(len(g[q]))
             assert abs(g[q][i] - fd) <= 1e-3 * max(abs(fd), scale), (q, i, g[q][i], fd)
     pb.close()
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    prob = W.c2_xpinn_poisson(seed=3, scale=0.1)
+    _say("autotune")
+    pb, lt0, g0 = run(prob)
+    cache = tmp_path / "tune.jsonl"
+    choice = pb.autotune(iters=2, cache_path=cache)
+    assert cache.exists() and len(cache.read_text().splitlines()) == 1
+    lt1, g1 = pb.loss_and_grad()
+    torch.cuda.synchronize()
+    compare(prob, [s.params for s in prob.subdomains], lt1.cpu().numpy(), [x.cpu().numpy() for x in pb.split(g1.cpu())])
+    # a second problem with the same signature takes the cached choice without a search
+    pb2 = ddpinn.Problem(prob, fused=True)
+    assert pb2.autotune(iters=2, cache_path=cache) == choice
+    assert len(cache.read_text().splitlines()) == 1
+    pb.step(2)
+    pb.sync()
+    pb.close()
+    pb2.close()
