@@ -774,8 +774,15 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
 
 // Persistent kernel: workgroups pull items (in descending cost order) from a
 // device counter until the list is drained.
+// Widths up to 64 fit two waves per SIMD (<= 256 registers); wider classes
+// run one wave per SIMD.
+template <int WPMAX>
+constexpr int min_waves_per_eu() {
+  return WPMAX <= 64 ? 2 : 1;
+}
+
 template <int WPMAX, int PDE>
-__global__ __launch_bounds__(NT) void k_train(KArgs ka) {
+__global__ __launch_bounds__(NT, min_waves_per_eu<WPMAX>()) void k_train(KArgs ka) {
   extern __shared__ float lds[];
   __shared__ int s_item;
   float* slot = ka.scratch + (int64_t)blockIdx.x * ka.scratch_slot;
