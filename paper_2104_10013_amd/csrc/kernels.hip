@@ -273,27 +273,41 @@ struct Tile {
     for (int idx = tid; idx < N4; idx += NT) d4[idx] = s4[idx];
   }
 
-  // a^k = W^k h^{k-1} (+ b^k on the value stream), all four streams
-  __device__ static void hidden_fwd(const float* sW, const float* bias, int g, int pc, const Streams& H,
-                                    Streams& A) {
+  // One hidden layer, output block by output block: a^k_mb = W^k h^{k-1}
+  // (+ b^k on the value stream) for all four streams, stash a^k_mb, and the
+  // tanh rule into the new activations Hn (H stays intact as the B operand).
+  template <bool STASH>
+  __device__ static void hidden_layer(const float* sW, const float* bias, int g, int pc, const Streams& H,
+                                      Streams& Hn, __amdgpu_buffer_rsrc_t rs, int layer, int wave, int lane) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      A[0][mb] = *reinterpret_cast<const f4*>(bias + 16 * mb + 4 * g);
-      A[1][mb] = f4{0.f, 0.f, 0.f, 0.f};
-      A[2][mb] = f4{0.f, 0.f, 0.f, 0.f};
-      A[3][mb] = f4{0.f, 0.f, 0.f, 0.f};
-    }
+      f4 acc[4];
+      acc[0] = *reinterpret_cast<const f4*>(bias + 16 * mb + 4 * g);
+      acc[1] = f4{0.f, 0.f, 0.f, 0.f};
+      acc[2] = f4{0.f, 0.f, 0.f, 0.f};
+      acc[3] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < MB; ++kb) {
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
+      for (int kb = 0; kb < MB; ++kb) {
         const f4 wv = *reinterpret_cast<const f4*>(&sW[(16 * mb + pc) * WS + 16 * kb + 4 * g]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
-          for (int s = 0; s < 4; ++s) A[s][mb] = mma(wv[i], H[s][kb][i], A[s][mb]);
+          for (int s = 0; s < 4; ++s) acc[s] = mma(wv[i], H[s][kb][i], acc[s]);
         }
+      }
+      if constexpr (STASH) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+          __builtin_amdgcn_raw_buffer_store_b128(acc[st], rs, lane * 16, stash_off(0, layer, wave, st, mb), 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float h, hx, hy, hl;
+        tanh_rule<S2>(acc[0][i], acc[1][i], acc[2][i], acc[3][i], h, hx, hy, hl);
+        Hn[0][mb][i] = h;
+        Hn[1][mb][i] = hx;
+        Hn[2][mb][i] = hy;
+        Hn[3][mb][i] = hl;
       }
     }
   }
@@ -468,15 +482,23 @@ struct Tile {
     const int gp = it.begin + tp;
     const float x = valid ? ka.if_xy[2 * (int64_t)gp] : 0.f;
     const float y = valid ? ka.if_xy[2 * (int64_t)gp + 1] : 0.f;
-    Streams A, H;
-    layer1(K, x, y, g, A);
-    activate(A, H);
+    Streams H;
+    {
+      Streams A;
+      layer1(K, x, y, g, A);
+      activate(A, H);
+    }
+    const __amdgpu_buffer_rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(sNb, 0, 0, 0x00020000);  // unused
     for (int k = 2; k <= nd.depth; ++k) {
       __syncthreads();
       stage(sW, K + L.k_w(k), tid);
       __syncthreads();
-      hidden_fwd(sW, K + L.k_b(k), g, pc, H, A);
-      activate(A, H);
+      Streams Hn;
+      hidden_layer<false>(sW, K + L.k_b(k), g, pc, H, Hn, none, 0, wave, lane);
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) H[st][mb] = Hn[st][mb];
     }
     float u[DO][4];
     out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
@@ -498,10 +520,6 @@ struct Tile {
     float* sU = sH + WP * TPS;       // [4 streams][3 outputs][TP]
     float* sX = sU + 4 * 3 * TP;     // [2][TP]
     float* sRed = sX + 2 * TP;       // [kWaves][kLossTerms]
-    const int tid = item_tid();
-    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int g = lane >> 4, pc = lane & 15;
-    const int tp = wave * 16 + pc;
     const int D = nd.depth;
     const Layout L(WP, D, DO);
     const float* K = ka.kparams + nd.koff;
@@ -511,6 +529,11 @@ struct Tile {
         __builtin_amdgcn_make_buffer_rsrc(slot, 0, (int)(ka.scratch_slot * sizeof(float)), 0x00020000);
 
     for (int t0 = 0; t0 < it.count; t0 += TP) {
+      // lane indices re-derived per tile (see item_tid)
+      int tid = item_tid();
+      int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+      int g = lane >> 4, pc = lane & 15;
+      int tp = wave * 16 + pc;
       const bool first = t0 == 0;
       const int pt = t0 + tp;
       const bool valid = pt < it.count;
@@ -524,17 +547,29 @@ struct Tile {
       }
 
       // ---- forward: Taylor streams through every layer, stash a^k
-      Streams A, H;
-      layer1(K, x, y, g, A);
-      activate(A, H);
+      Streams H;
+      {
+        Streams A;
+        layer1(K, x, y, g, A);
+        activate(A, H);
+      }
       for (int k = 2; k <= D; ++k) {
+        tid = item_tid();
+        lane = tid & 63;
+        wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        g = lane >> 4;
+        pc = lane & 15;
+        tp = wave * 16 + pc;
         stash_store(rs, 1, k - 2, wave, lane, H);   // h^{k-1}
         __syncthreads();
         stage(sW, K + L.k_w(k), tid);
         __syncthreads();
-        hidden_fwd(sW, K + L.k_b(k), g, pc, H, A);
-        stash_store(rs, 0, k - 2, wave, lane, A);   // a^k
-        activate(A, H);
+        Streams Hn;
+        hidden_layer<true>(sW, K + L.k_b(k), g, pc, H, Hn, rs, k - 2, wave, lane);   // stashes a^k
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) H[st][mb] = Hn[st][mb];
       }
       float u[DO][4];
       out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
@@ -613,8 +648,18 @@ struct Tile {
         accum(ka.loss_part + (int64_t)it.lrow * kLossTerms + tid, v * it.inv_n, first);
       }
 
-      // ---- hidden layers, top down
+      // ---- hidden layers, top down.  g^k arrives in registers for k = D and
+      // from the stash below (written into the slot of a^{k+1}, which is dead
+      // by then), so the reverse pass holds one layer of streams at a time.
       for (int k = D; k >= 2; --k) {
+        // and again per layer, so address arithmetic is not pinned across layers
+        tid = item_tid();
+        lane = tid & 63;
+        wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        g = lane >> 4;
+        pc = lane & 15;
+        tp = wave * 16 + pc;
+        if (k < D) stash_load(rs, 0, k - 1, wave, lane, G);
         // abar^k from the stashed a^k and the incoming g^k (in place of g^k)
         {
           Streams Ak;
@@ -642,13 +687,18 @@ struct Tile {
 #pragma unroll
         for (int r = 0; r < NB; ++r) dacc[r] = f4{0.f, 0.f, 0.f, 0.f};
         float dbias = 0.f;
-        Streams Gn;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           f4 Hs[MB];
           stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s
           __syncthreads();
-          hidden_bwd_stream(sW, g, pc, Ab[s], Gn[s]);
+          {
+            f4 Gs[MB];
+            hidden_bwd_stream(sW, g, pc, Ab[s], Gs);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)   // g^{k-1}_s into the slot of a^k
+              __builtin_amdgcn_raw_buffer_store_b128(Gs[mb], rs, lane * 16, stash_off(0, k - 2, wave, s, mb), 0);
+          }
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -674,10 +724,6 @@ struct Tile {
           }
           if (s == 0 && tid < WP) dbias = row_sum(sA + tid * TPS);
         }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) G[s][mb] = Gn[s][mb];
         float* Rw = R + L.g_w(k);
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
@@ -693,6 +739,7 @@ struct Tile {
 
       // ---- layer 1: abar^1 from a^1 and g^1; dW^1 and db^1 are sums over points
       {
+        if (D >= 2) stash_load(rs, 0, 0, wave, lane, G);   // g^1
         Streams A1;
         layer1(K, x, y, g, A1);
         __syncthreads();
@@ -774,11 +821,11 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
 
 // Persistent kernel: workgroups pull items (in descending cost order) from a
 // device counter until the list is drained.
-// Widths up to 64 fit two waves per SIMD (<= 256 registers); wider classes
+// Widths up to 80 fit two waves per SIMD (<= 256 registers); wider classes
 // run one wave per SIMD.
 template <int WPMAX>
 constexpr int min_waves_per_eu() {
-  return WPMAX <= 64 ? 2 : 1;
+  return WPMAX <= 80 ? 2 : 1;
 }
 
 template <int WPMAX, int PDE>
