@@ -41,6 +41,25 @@ constexpr int TP = kTilePts;      // points per tile
 constexpr int TPS = kTilePts + 4; // LDS row stride of staged tiles (floats)
 constexpr int NT = 64 * kWaves;   // threads per workgroup
 
+// Wait until this wave's outstanding vector-memory stores have completed.
+// The stash and the partial rows are written and later re-read by the same
+// wave; the compiler orders those accesses only through registers, so every
+// re-read of stored data is preceded by this wait (and reads at device scope,
+// so no vector-L1 copy from before the store is used).
+// One 16-byte-per-lane store into the activation stash, followed by wait
+// states before anything may overwrite its data registers.  The compiler
+// treats a buffer store with an SGPR offset as free of the store-data
+// overwrite hazard and will reuse the data VGPRs in the next instruction; with
+// two waves per SIMD such stores were seen to write the later value now and
+// then (the adjoint round trip through the stash came back wrong for a few
+// points), and the padding below removes that.
+__device__ __forceinline__ void stash_put(f4 v, __amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, rs, voff, soff, 0);
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 4");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // Per-item copy of the thread index the compiler cannot treat as loop
 // invariant: keeps per-lane address arithmetic of every width class from being
 // hoisted out of the persistent item loop (where it would pin registers).
@@ -298,7 +317,7 @@ struct Tile {
       if constexpr (STASH) {
 #pragma unroll
         for (int st = 0; st < 4; ++st)
-          __builtin_amdgcn_raw_buffer_store_b128(acc[st], rs, lane * 16, stash_off(0, layer, wave, st, mb), 0);
+          stash_put(acc[st], rs, lane * 16, stash_off(0, layer, wave, st, mb));
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -342,21 +361,25 @@ struct Tile {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
-        __builtin_amdgcn_raw_buffer_store_b128(A[s][mb], rs, lane * 16, stash_off(region, layer, wave, s, mb), 0);
+        stash_put(A[s][mb], rs, lane * 16, stash_off(region, layer, wave, s, mb));
   }
+  // Stash loads read at device scope (SC1): a slot is rewritten by the same
+  // wave between loads (a^k -> g^{k-1}, and every tile), and the per-CU vector
+  // L1 must not serve a copy from before the rewrite.
+  static constexpr int kStashLoadPolicy = 16;
   __device__ static void stash_load(__amdgpu_buffer_rsrc_t rs, int region, int layer, int wave, int lane,
                                     Streams& A) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
-        A[s][mb] = __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, stash_off(region, layer, wave, s, mb), 0);
+        A[s][mb] = __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, stash_off(region, layer, wave, s, mb), kStashLoadPolicy);
   }
   __device__ static void stash_load_stream(__amdgpu_buffer_rsrc_t rs, int region, int layer, int wave, int lane,
                                            int s, f4 (&As)[MB]) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
-      As[mb] = __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, stash_off(region, layer, wave, s, mb), 0);
+      As[mb] = __builtin_amdgcn_raw_buffer_load_b128(rs, lane * 16, stash_off(region, layer, wave, s, mb), kStashLoadPolicy);
   }
 
   // output layer u = W^L h + b^L for DO outputs; every lane group ends with
@@ -460,9 +483,11 @@ struct Tile {
     }
   }
 
+  // gradient / loss partial rows: written by the first tile of an item,
+  // accumulated by the following ones (read at device scope, as for the stash)
   __device__ static void accum(float* dst, float v, bool first) {
     if (first) *dst = v;
-    else *dst += v;
+    else *dst = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + v;
   }
 
   // ------------------------------------------------------------------------
@@ -659,7 +684,7 @@ struct Tile {
         g = lane >> 4;
         pc = lane & 15;
         tp = wave * 16 + pc;
-        if (k < D) stash_load(rs, 0, k - 1, wave, lane, G);
+          if (k < D) stash_load(rs, 0, k - 1, wave, lane, G);
         // abar^k from the stashed a^k and the incoming g^k (in place of g^k)
         {
           Streams Ak;
@@ -690,14 +715,14 @@ struct Tile {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           f4 Hs[MB];
-          stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s
+          stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s (stored in the forward)
           __syncthreads();
           {
             f4 Gs[MB];
             hidden_bwd_stream(sW, g, pc, Ab[s], Gs);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)   // g^{k-1}_s into the slot of a^k
-              __builtin_amdgcn_raw_buffer_store_b128(Gs[mb], rs, lane * 16, stash_off(0, k - 2, wave, s, mb), 0);
+              stash_put(Gs[mb], rs, lane * 16, stash_off(0, k - 2, wave, s, mb));
           }
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb)
@@ -739,7 +764,7 @@ struct Tile {
 
       // ---- layer 1: abar^1 from a^1 and g^1; dW^1 and db^1 are sums over points
       {
-        if (D >= 2) stash_load(rs, 0, 0, wave, lane, G);   // g^1
+          if (D >= 2) stash_load(rs, 0, 0, wave, lane, G);   // g^1
         Streams A1;
         layer1(K, x, y, g, A1);
         __syncthreads();
@@ -769,12 +794,10 @@ struct Tile {
         __syncthreads();
         if (tid < WP) {
           dw1 = row_dot_plus(sA + tid * TPS, sX + TP, sH + tid * TPS);
-          if (first) {
-            *reinterpret_cast<f4*>(R + 4 * tid) = f4{dw0, dw1, db, 0.f};
-          } else {
-            f4 o = *reinterpret_cast<f4*>(R + 4 * tid);
-            *reinterpret_cast<f4*>(R + 4 * tid) = f4{o[0] + dw0, o[1] + dw1, o[2] + db, 0.f};
-          }
+          accum(R + 4 * tid, dw0, first);
+          accum(R + 4 * tid + 1, dw1, first);
+          accum(R + 4 * tid + 2, db, first);
+          if (first) R[4 * tid + 3] = 0.f;
         }
       }
     }
@@ -784,6 +807,13 @@ struct Tile {
 template <int WP, int PDE>
 constexpr int lds_train_floats() {
   return WP * (WP + 4) + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms + 6 * TP;
+}
+
+// bytes of dynamic LDS the train kernel is launched with: the tile buffers and
+// one 16-byte slot for the work-item broadcast
+template <int WP, int PDE>
+constexpr int lds_train_bytes() {
+  return lds_train_floats<WP, PDE>() * 4 + 16;
 }
 
 // Run one item: for an interface item first evaluate the neighbour's network
@@ -830,8 +860,11 @@ constexpr int min_waves_per_eu() {
 
 template <int WPMAX, int PDE>
 __global__ __launch_bounds__(NT, min_waves_per_eu<WPMAX>()) void k_train(KArgs ka) {
-  extern __shared__ float lds[];
-  __shared__ int s_item;
+  // one 16-byte aligned dynamic LDS block: the tile buffers, then the slot
+  // that broadcasts the next work item (no static LDS, so the float4
+  // accesses of the tile buffers stay 16-byte aligned)
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  int& s_item = *reinterpret_cast<int*>(lds + lds_train_floats<WPMAX, PDE>());
   float* slot = ka.scratch + (int64_t)blockIdx.x * ka.scratch_slot;
   if (ka.prologue && blockIdx.x == 0 && threadIdx.x == 0) {
     // settle the Adam step counter of the previous update (k_reduce reads it)
@@ -1039,9 +1072,9 @@ struct KTable {
       (const void*)k_train<64, PDE>, (const void*)k_train<80, PDE>, (const void*)k_train<96, PDE>, \
       (const void*)k_train<112, PDE>};                                                          \
   template <> int KTable<PDE>::lds[7] = {                                                       \
-      lds_train_floats<16, PDE>(), lds_train_floats<32, PDE>(), lds_train_floats<48, PDE>(),    \
-      lds_train_floats<64, PDE>(), lds_train_floats<80, PDE>(), lds_train_floats<96, PDE>(),    \
-      lds_train_floats<112, PDE>()};
+      lds_train_bytes<16, PDE>(), lds_train_bytes<32, PDE>(), lds_train_bytes<48, PDE>(),       \
+      lds_train_bytes<64, PDE>(), lds_train_bytes<80, PDE>(), lds_train_bytes<96, PDE>(),       \
+      lds_train_bytes<112, PDE>()};
 DDP_ROW(PDE_POISSON)
 DDP_ROW(PDE_BURGERS)
 DDP_ROW(PDE_NS)
@@ -1067,7 +1100,7 @@ size_t lds_bytes(int pde, int wpmax) {
     case PDE_BURGERS: f = KTable<PDE_BURGERS>::lds[c]; break;
     case PDE_NS: f = KTable<PDE_NS>::lds[c]; break;
   }
-  return (size_t)f * sizeof(float);
+  return (size_t)f;
 }
 
 int64_t scratch_slot_floats(int wpmax) {
