@@ -112,10 +112,9 @@ struct RArgs {
   const float* loss_part;
   const NetDesc* nets;
   const int64_t* sd_poff;     // n_sd + 1 prefix of parameter offsets
-  const int* sd_rows;         // CSR over subdomains of item indices
-  const int* sd_row_ptr;      // n_sd + 1
-  const int64_t* row_prow;    // per item: gradient partial offset
-  const int* row_lrow;        // per item: loss row
+  const int* sd_row_ptr;      // n_sd + 1: CSR over subdomains of the partial rows
+  const int64_t* row_prow;    // per CSR row: gradient partial offset
+  const int* row_lrow;        // per CSR row: loss row
   int n_sd;
   int q_begin, q_end;         // subdomain range handled by this launch
   float* grad_out;            // gradient output or nullptr

@@ -110,7 +110,7 @@ struct ddp_problem {
   float* d_if_xy = nullptr;
   float *d_partial = nullptr, *d_loss_part = nullptr, *d_scratch = nullptr, *d_loss = nullptr;
   int64_t* d_sd_poff = nullptr;
-  int *d_sd_rows = nullptr, *d_sd_row_ptr = nullptr, *d_row_lrow = nullptr;
+  int *d_sd_row_ptr = nullptr, *d_row_lrow = nullptr;
   int64_t* d_row_prow = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -329,11 +329,13 @@ int build_plan(ddp_problem* p) {
     std::vector<int> fill(p->sd_row_ptr.begin(), p->sd_row_ptr.end() - 1);
     for (int i = 0; i < (int)p->titems.size(); ++i) p->sd_rows[fill[p->titems[i].q]++] = i;
   }
+  // partial and loss row offsets in the same CSR order, so the reduction
+  // reads them without going through the item list
   p->row_prow.resize(p->titems.size());
   p->row_lrow.resize(p->titems.size());
-  for (size_t i = 0; i < p->titems.size(); ++i) {
-    p->row_prow[i] = p->titems[i].prow;
-    p->row_lrow[i] = p->titems[i].lrow;
+  for (size_t r = 0; r < p->sd_rows.size(); ++r) {
+    p->row_prow[r] = p->titems[p->sd_rows[r]].prow;
+    p->row_lrow[r] = p->titems[p->sd_rows[r]].lrow;
   }
   p->planned = true;
   return DDP_OK;
@@ -370,7 +372,6 @@ RArgs make_rargs(ddp_problem* p) {
   ra.loss_part = p->d_loss_part;
   ra.nets = p->d_nets;
   ra.sd_poff = p->d_sd_poff;
-  ra.sd_rows = p->d_sd_rows;
   ra.sd_row_ptr = p->d_sd_row_ptr;
   ra.row_prow = p->d_row_prow;
   ra.row_lrow = p->d_row_lrow;
@@ -623,7 +624,6 @@ int install_plan(ddp_problem* p) {
   if ((rc = plan_alloc(p, &p->d_partial, (size_t)p->partial_floats))) return rc;
   if ((rc = plan_alloc(p, &p->d_loss_part, p->titems.size() * kLossTerms))) return rc;
   if ((rc = plan_alloc(p, &p->d_scratch, (size_t)p->n_slots * p->slot_floats))) return rc;
-  if ((rc = plan_upload(p, &p->d_sd_rows, p->sd_rows))) return rc;
   if ((rc = plan_upload(p, &p->d_sd_row_ptr, p->sd_row_ptr))) return rc;
   if ((rc = plan_upload(p, &p->d_row_prow, p->row_prow))) return rc;
   if ((rc = plan_upload(p, &p->d_row_lrow, p->row_lrow))) return rc;

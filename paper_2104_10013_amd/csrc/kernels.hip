@@ -936,8 +936,14 @@ __device__ __forceinline__ int find_sd(const int64_t* sd_poff, int q, int64_t i)
 
 // Sum each subdomain's gradient partial rows in a fixed order, then write the
 // gradient and/or apply Adam (Kingma-Ba, bias corrected) and refresh the
-// kernel-layout copy; block 0 also sums the loss rows and flags non-finite
-// losses.
+// kernel-layout copy; the waves of block 0 also sum the loss rows and flag
+// non-finite losses.
+//
+// A thread owns one parameter and keeps kRedLanes independent partial sums over
+// the rows (row r goes to sum r mod kRedLanes), combined by a fixed tree: the
+// loads of a batch are independent, and the order does not depend on timing.
+constexpr int kRedLanes = 16;
+
 __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
   const int64_t p0 = ra.sd_poff[ra.q_begin], p1 = ra.sd_poff[ra.q_end];
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
@@ -950,8 +956,25 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
     const NetDesc nd = ra.nets[q];
     int gi, k1, k2;
     param_map(nd, (int)(i - ra.sd_poff[q]), gi, k1, k2);
-    float s = 0.f;
-    for (int r = ra.sd_row_ptr[q]; r < ra.sd_row_ptr[q + 1]; ++r) s += ra.partial[ra.row_prow[ra.sd_rows[r]] + gi];
+    const int r0 = ra.sd_row_ptr[q], n = ra.sd_row_ptr[q + 1] - r0;
+    const int64_t* pr = ra.row_prow + r0;
+    const float* P = ra.partial + gi;
+    float a[kRedLanes];
+#pragma unroll
+    for (int j = 0; j < kRedLanes; ++j) a[j] = 0.f;
+    int r = 0;
+    for (; r + kRedLanes <= n; r += kRedLanes) {
+#pragma unroll
+      for (int j = 0; j < kRedLanes; ++j) a[j] += P[pr[r + j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kRedLanes; ++j)
+      if (r + j < n) a[j] += P[pr[r + j]];
+#pragma unroll
+    for (int w = kRedLanes / 2; w >= 1; w /= 2)
+#pragma unroll
+      for (int j = 0; j < w; ++j) a[j] += a[j + w];
+    const float s = a[0];
     if (ra.grad_out) ra.grad_out[i] = s;
     if (ra.do_adam) {
       const float m = b1 * ra.adam_m[i] + (1.f - b1) * s;
@@ -968,20 +991,27 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
     }
   }
   if (blockIdx.x == 0) {
-    for (int q = ra.q_begin + threadIdx.x; q < ra.q_end; q += blockDim.x) {
+    // one wave per subdomain: lane l sums rows l, l + 64, ...; then a fixed
+    // butterfly across the wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = ra.q_begin + wave; q < ra.q_end; q += (int)(blockDim.x >> 6)) {
       float t[kLossTerms] = {0.f, 0.f, 0.f, 0.f};
-      for (int r = ra.sd_row_ptr[q]; r < ra.sd_row_ptr[q + 1]; ++r) {
-        const float* lp = ra.loss_part + (int64_t)ra.row_lrow[ra.sd_rows[r]] * kLossTerms;
+      for (int r = ra.sd_row_ptr[q] + lane; r < ra.sd_row_ptr[q + 1]; r += 64) {
+        const float* lp = ra.loss_part + (int64_t)ra.row_lrow[r] * kLossTerms;
         for (int k = 0; k < kLossTerms; ++k) t[k] += lp[k];
       }
-      const NetDesc nd = ra.nets[q];
-      float J = 0.f;
-      for (int k = 0; k < kLossTerms; ++k) J += nd.loss_w[k] * t[k];
-      if (ra.loss_out) {
-        ra.loss_out[q * 5] = J;
-        for (int k = 0; k < kLossTerms; ++k) ra.loss_out[q * 5 + 1 + k] = t[k];
+      for (int k = 0; k < kLossTerms; ++k)
+        for (int m = 32; m >= 1; m >>= 1) t[k] += __shfl_xor(t[k], m);
+      if (lane == 0) {
+        const NetDesc nd = ra.nets[q];
+        float J = 0.f;
+        for (int k = 0; k < kLossTerms; ++k) J += nd.loss_w[k] * t[k];
+        if (ra.loss_out) {
+          ra.loss_out[q * 5] = J;
+          for (int k = 0; k < kLossTerms; ++k) ra.loss_out[q * 5 + 1 + k] = t[k];
+        }
+        if (!isfinite(J)) ra.flags[0] = 1;
       }
-      if (!isfinite(J)) ra.flags[0] = 1;
     }
     if (ra.do_adam && threadIdx.x == 0) ra.tstate[1] = 1;
     // the train kernel of this step has finished: re-arm its work counter
