@@ -51,8 +51,8 @@ constexpr int NT = 64 * kWaves;   // threads per workgroup
 // treats a buffer store with an SGPR offset as free of the store-data
 // overwrite hazard and will reuse the data VGPRs in the next instruction; with
 // two waves per SIMD such stores were seen to write the later value now and
-// then (the adjoint round trip through the stash came back wrong for a few
-// points), and the padding below removes that.
+// then (values read back from the stash came back wrong for a few points),
+// and the padding below removes that.
 __device__ __forceinline__ void stash_put(f4 v, __amdgpu_buffer_rsrc_t rs, int voff, int soff) {
   __builtin_amdgcn_raw_buffer_store_b128(v, rs, voff, soff, 0);
   __builtin_amdgcn_sched_barrier(0);
@@ -364,8 +364,8 @@ struct Tile {
         stash_put(A[s][mb], rs, lane * 16, stash_off(region, layer, wave, s, mb));
   }
   // Stash loads read at device scope (SC1): a slot is rewritten by the same
-  // wave between loads (a^k -> g^{k-1}, and every tile), and the per-CU vector
-  // L1 must not serve a copy from before the rewrite.
+  // wave on every tile, and the per-CU vector L1 must not serve a copy from
+  // before the rewrite.
   static constexpr int kStashLoadPolicy = 16;
   __device__ static void stash_load(__amdgpu_buffer_rsrc_t rs, int region, int layer, int wave, int lane,
                                     Streams& A) {
@@ -673,9 +673,10 @@ struct Tile {
         accum(ka.loss_part + (int64_t)it.lrow * kLossTerms + tid, v * it.inv_n, first);
       }
 
-      // ---- hidden layers, top down.  g^k arrives in registers for k = D and
-      // from the stash below (written into the slot of a^{k+1}, which is dead
-      // by then), so the reverse pass holds one layer of streams at a time.
+      // ---- hidden layers, top down.  G holds g^k on entry to layer k; it is
+      // turned into abar^k in place, and stream by stream each abar^k_s is
+      // replaced by g^{k-1}_s once it has been staged for dW^k, so the reverse
+      // pass holds one layer of streams plus one stream in flight.
       for (int k = D; k >= 2; --k) {
         // and again per layer, so address arithmetic is not pinned across layers
         tid = item_tid();
@@ -684,7 +685,6 @@ struct Tile {
         g = lane >> 4;
         pc = lane & 15;
         tp = wave * 16 + pc;
-          if (k < D) stash_load(rs, 0, k - 1, wave, lane, G);
         // abar^k from the stashed a^k and the incoming g^k (in place of g^k)
         {
           Streams Ak;
@@ -721,16 +721,15 @@ struct Tile {
             f4 Gs[MB];
             hidden_bwd_stream(sW, g, pc, Ab[s], Gs);
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)   // g^{k-1}_s into the slot of a^k
-              stash_put(Gs[mb], rs, lane * 16, stash_off(0, k - 2, wave, s, mb));
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                sA[(16 * mb + 4 * g + i) * TPS + tp] = Ab[s][mb][i];
+                sH[(16 * mb + 4 * g + i) * TPS + tp] = Hs[mb][i];
+              }
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) G[s][mb] = Gs[mb];   // g^{k-1}_s replaces abar^k_s
           }
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              sA[(16 * mb + 4 * g + i) * TPS + tp] = Ab[s][mb][i];
-              sH[(16 * mb + 4 * g + i) * TPS + tp] = Hs[mb][i];
-            }
           __syncthreads();
 #pragma unroll
           for (int r = 0; r < NB; ++r) {
@@ -764,8 +763,7 @@ struct Tile {
 
       // ---- layer 1: abar^1 from a^1 and g^1; dW^1 and db^1 are sums over points
       {
-          if (D >= 2) stash_load(rs, 0, 0, wave, lane, G);   // g^1
-        Streams A1;
+          Streams A1;
         layer1(K, x, y, g, A1);
         __syncthreads();
 #pragma unroll
