@@ -489,6 +489,12 @@ struct Tile {
     if (first) *dst = v;
     else *dst = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + v;
   }
+  // the value a partial-row entry holds before this tile (0 on an item's first
+  // tile): loaded early into the accumulator, so the tile's sums add onto it
+  // and the entry is then simply stored
+  __device__ static float prior(const float* src, bool first) {
+    return first ? 0.f : __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 
   // ------------------------------------------------------------------------
   // forward only: the values this network contributes on the interface points
@@ -537,6 +543,10 @@ struct Tile {
 
   // ------------------------------------------------------------------------
   // forward, loss, adjoint and parameter-gradient partials of one item
+  //
+  // PREFETCH_A: load a^{k-1} during layer k of the reverse pass (and a^D while
+  // the output layer runs) instead of at the top of each reverse layer.
+  template <bool PREFETCH_A>
   __device__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                    float* slot, const float* sNb) {
     float* sW = lds;
@@ -639,10 +649,17 @@ struct Tile {
           }
         }
       }
+      // a^D for the first reverse layer, loaded while the output layer runs
+      // (where registers allow; else at the top of each reverse layer)
+      Streams Ak;
+      if (PREFETCH_A && D >= 2) stash_load(rs, 0, D - 2, wave, lane, Ak);
       float accL[KL];
 #pragma unroll
-      for (int r = 0; r < KL; ++r) accL[r] = 0.f;
-      float accB = 0.f;
+      for (int r = 0; r < KL; ++r) {
+        const int t = tid + r * NT;
+        accL[r] = t < DO * WP ? prior(R + L.g_out() + t, first) : 0.f;
+      }
+      float accB = tid < DO ? prior(R + L.g_bout() + tid, first) : 0.f;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         __syncthreads();
@@ -659,14 +676,14 @@ struct Tile {
             accL[r] = row_dot(sU + (s * 3 + c) * TP, sH + j * TPS, accL[r]);
           }
         }
-        if (s == 0 && tid < DO) accB = row_sum(sU + tid * TP);
+        if (s == 0 && tid < DO) accB += row_sum(sU + tid * TP);
       }
 #pragma unroll
       for (int r = 0; r < KL; ++r) {
         const int t = tid + r * NT;
-        if (t < DO * WP) accum(R + L.g_out() + t, accL[r], first);
+        if (t < DO * WP) R[L.g_out() + t] = accL[r];
       }
-      if (tid < DO) accum(R + L.g_bout() + tid, accB, first);
+      if (tid < DO) R[L.g_bout() + tid] = accB;
       if (tid < kLossTerms) {
         float v = 0.f;
         for (int wv = 0; wv < kWaves; ++wv) v += sRed[wv * kLossTerms + tid];
@@ -685,10 +702,24 @@ struct Tile {
         g = lane >> 4;
         pc = lane & 15;
         tp = wave * 16 + pc;
-        // abar^k from the stashed a^k and the incoming g^k (in place of g^k)
+        // dW^k / db^k accumulators start from the partial row
+        float* Rw = R + L.g_w(k);
+        f4 dacc[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          const int b = wave + r * kWaves;
+          if (b < NBT) {
+            const int mb = b / MB, jb = b - (b / MB) * MB;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dacc[r][i] = prior(Rw + (16 * mb + 4 * g + i) * WP + 16 * jb + pc, first);
+          } else {
+            dacc[r] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+        float dbias = tid < WP ? prior(R + L.g_b(k) + tid, first) : 0.f;
+        // abar^k from the stashed a^k (loaded ahead) and the incoming g^k (in place of g^k)
         {
-          Streams Ak;
-          stash_load(rs, 0, k - 2, wave, lane, Ak);
+          if (!PREFETCH_A) stash_load(rs, 0, k - 2, wave, lane, Ak);
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -708,10 +739,6 @@ struct Tile {
         stage(sW, K + L.k_wt(k), tid);
         // per stream: g^{k-1}_s = W^{kT} abar^k_s, then the stream's share of
         // dW^k = sum_{points, streams} abar^k h^{k-1 T}; db^k = sum_points abar^k_0
-        f4 dacc[NB];
-#pragma unroll
-        for (int r = 0; r < NB; ++r) dacc[r] = f4{0.f, 0.f, 0.f, 0.f};
-        float dbias = 0.f;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           f4 Hs[MB];
@@ -730,6 +757,8 @@ struct Tile {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) G[s][mb] = Gs[mb];   // g^{k-1}_s replaces abar^k_s
           }
+          // a^{k-1} for the next reverse layer, loaded during the last dW^k stream
+          if (PREFETCH_A && s == 3 && k > 2) stash_load(rs, 0, k - 3, wave, lane, Ak);
           __syncthreads();
 #pragma unroll
           for (int r = 0; r < NB; ++r) {
@@ -746,24 +775,29 @@ struct Tile {
               }
             }
           }
-          if (s == 0 && tid < WP) dbias = row_sum(sA + tid * TPS);
+          if (s == 0 && tid < WP) dbias += row_sum(sA + tid * TPS);
         }
-        float* Rw = R + L.g_w(k);
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
           const int b = wave + r * kWaves;
           if (b < NBT) {
             const int mb = b / MB, jb = b - (b / MB) * MB;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) accum(Rw + (16 * mb + 4 * g + i) * WP + 16 * jb + pc, dacc[r][i], first);
+            for (int i = 0; i < 4; ++i) Rw[(16 * mb + 4 * g + i) * WP + 16 * jb + pc] = dacc[r][i];
           }
         }
-        if (tid < WP) accum(R + L.g_b(k) + tid, dbias, first);
+        if (tid < WP) R[L.g_b(k) + tid] = dbias;
       }
 
       // ---- layer 1: abar^1 from a^1 and g^1; dW^1 and db^1 are sums over points
       {
-          Streams A1;
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+        if (tid < WP) {
+          p0 = prior(R + 4 * tid, first);
+          p1 = prior(R + 4 * tid + 1, first);
+          p2 = prior(R + 4 * tid + 2, first);
+        }
+        Streams A1;
         layer1(K, x, y, g, A1);
         __syncthreads();
 #pragma unroll
@@ -792,13 +826,22 @@ struct Tile {
         __syncthreads();
         if (tid < WP) {
           dw1 = row_dot_plus(sA + tid * TPS, sX + TP, sH + tid * TPS);
-          accum(R + 4 * tid, dw0, first);
-          accum(R + 4 * tid + 1, dw1, first);
-          accum(R + 4 * tid + 2, db, first);
+          R[4 * tid] = p0 + dw0;
+          R[4 * tid + 1] = p1 + dw1;
+          R[4 * tid + 2] = p2 + db;
           if (first) R[4 * tid + 3] = 0.f;
         }
       }
     }
+  }
+
+  // entry from a kernel built for classes up to WPMAX: the a^k prefetch costs
+  // registers, so it is used for classes up to 48 in kernels that run two
+  // waves per SIMD anyway because of a wider class
+  template <int WPMAX>
+  __device__ static void train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* slot,
+                               const float* sNb) {
+    run_train<(WP <= 48 && WPMAX >= 48)>(ka, it, nd, lds, slot, sNb);
   }
 };
 
@@ -842,7 +885,7 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
     DDP_SWITCH(ndn.wclass, values_tile(ka, it, ndn, lds, sNb))
     __syncthreads();
   }
-  DDP_SWITCH(nd.wclass, run_train(ka, it, nd, lds, slot, sNb))
+  DDP_SWITCH(nd.wclass, template train<WPMAX>(ka, it, nd, lds, slot, sNb))
 #undef DDP_SWITCH
 #undef DDP_CASE
 }
