@@ -11,7 +11,9 @@ are the float32 values the GPU sees, converted exactly):
 * input derivatives of the network output by automatic differentiation, as the
   paper does for the PDE residual (Sec. 4.1);
 * the residual F = L_x(u) - f of Eq. ProSet for the Poisson, Burgers (Eq. BE)
-  and steady Navier-Stokes (Eq. NSEq) operators;
+  and steady Navier-Stokes (Eq. NSEq) operators, and for the inverse
+  diffusion problem of Eq. heq, div(K grad u) = f, where the conductivity K is
+  a second network of the subdomain (Sec. 7.6);
 * the per-subdomain losses J(Theta_q) of Eq. cPINNLoss (data, residual,
   average-solution and normal-flux terms) and Eq. XPINNLoss (data, residual,
   average-solution and residual-continuity terms);
@@ -20,7 +22,8 @@ are the float32 values the GPU sees, converted exactly):
   received from its neighbours;
 * one Adam step per subdomain (Sec. 6; Kingma-Ba form, beta=(0.9,0.999),
   eps=1e-8);
-* the stitched solution of Eq. FSol with the 1/S indicator on interfaces.
+* the stitched solution of Eq. FSol with the 1/S indicator on interfaces
+  (for the inverse problem both u and K are stitched).
 
 Plain PyTorch CPU ops in float64 serve as the library primitives (matmul, tanh,
 reverse-mode differentiation).  There is no blocking, fusion or reordering.
@@ -36,6 +39,7 @@ DT = torch.float64
 POISSON2D = "poisson2d"
 BURGERS1D = "burgers1d"
 NS2D = "ns2d_steady"
+DIFF_INV = "diffusion2d_inv"
 
 
 # ----------------------------------------------------------------------------
@@ -124,6 +128,23 @@ def residual(pde, coef, st, f):
     raise ValueError(pde)
 
 
+def residual_inverse(stu, stk, f):
+    """Eq. heq with the divergence expanded: F = K Lap u + K_x u_x + K_y u_y - f,
+    from the u-network streams stu and the K-network streams stk; (N, 1)."""
+    K, dK = stk["u"][:, 0], stk["du"][:, 0]
+    du, lap = stu["du"][:, 0], stu["lap"][:, 0]
+    return (K * lap + dK[:, 0] * du[:, 0] + dK[:, 1] * du[:, 1] - f[:, 0])[:, None]
+
+
+def split_theta(prob, q, theta):
+    """(solution-network params, K-network params or None) of subdomain q."""
+    sd = prob.subdomains[q]
+    if sd.aux_widths is None:
+        return theta, None
+    n = sum(sd.widths[k] * sd.widths[k - 1] + sd.widths[k] for k in range(1, len(sd.widths)))
+    return theta[:n], theta[n:]
+
+
 def normal_flux(pde, coef, st, n):
     """f(u) . n for the conservative form of the equation, shape (N, 1).
 
@@ -159,6 +180,16 @@ def interface_value(prob, q, theta, e, create_graph):
     """What subdomain q contributes on interface e: u, and flux.n (cPINN) or F (XPINN)."""
     sd = prob.subdomains[q]
     z = _t(e.xy)
+    if prob.pde == DIFF_INV:
+        # the pair (u, K) is the solution whose average is matched; the
+        # operator value L(u, K) = div(K grad u) is compared (f cancels)
+        if prob.method != "xpinn":
+            raise NotImplementedError("the inverse problem uses XPINN interfaces")
+        thu, thk = split_theta(prob, q, theta)
+        stu = input_streams(thu, sd.widths, z, prob.pde, create_graph=create_graph)
+        stk = input_streams(thk, sd.aux_widths, z, prob.pde, create_graph=create_graph)
+        f0 = torch.zeros((z.shape[0], 1), dtype=DT)
+        return torch.cat([stu["u"], stk["u"]], 1), residual_inverse(stu, stk, f0)
     st = input_streams(theta, sd.widths, z, prob.pde, create_graph=create_graph)
     u = st["u"]
     if prob.method == "cpinn":
@@ -179,17 +210,26 @@ def subdomain_terms(prob, q, thetas, grad_mode="local"):
     only by tests of the alternative readings)."""
     sd = prob.subdomains[q]
     th = thetas[q]
+    thu, thk = split_theta(prob, q, th)
     Wu, WF, WI, W4 = sd.loss_w
-    # data / boundary term
+    # data / boundary term (for the inverse problem also the K data; the two
+    # mean squares are summed like the components of a vector solution)
     if sd.bnd_xy.shape[0] > 0:
-        ub = mlp(th, sd.widths, _t(sd.bnd_xy))
+        ub = mlp(thu, sd.widths, _t(sd.bnd_xy))
         mse_u = _mean_sq(ub - _t(sd.bnd_g))
     else:
         mse_u = torch.zeros((), dtype=DT)
+    if thk is not None and sd.aux_xy.shape[0] > 0:
+        kb = mlp(thk, sd.aux_widths, _t(sd.aux_xy))
+        mse_u = mse_u + _mean_sq(kb - _t(sd.aux_g))
     # residual term
     if sd.res_xy.shape[0] > 0:
-        st = input_streams(th, sd.widths, _t(sd.res_xy), prob.pde)
-        F = residual(prob.pde, prob.coef, st, _t(sd.res_f))
+        st = input_streams(thu, sd.widths, _t(sd.res_xy), prob.pde)
+        if thk is None:
+            F = residual(prob.pde, prob.coef, st, _t(sd.res_f))
+        else:
+            stk = input_streams(thk, sd.aux_widths, _t(sd.res_xy), prob.pde)
+            F = residual_inverse(st, stk, _t(sd.res_f))
         mse_f = _mean_sq(F)
     else:
         mse_f = torch.zeros((), dtype=DT)
@@ -274,14 +314,19 @@ def eval_stitched(prob, params, xy, owner):
 
     owner[i] lists the S subdomains whose closure holds point i (-1 padded)."""
     xy = np.asarray(xy)
-    out = np.zeros((xy.shape[0], prob.d_out))
+    inv = prob.pde == DIFF_INV
+    out = np.zeros((xy.shape[0], prob.d_out + (1 if inv else 0)))
     cnt = (owner >= 0).sum(1)
     with torch.no_grad():
         for q in range(prob.n_sd):
             sel = np.nonzero((owner == q).any(1))[0]
             if sel.size == 0:
                 continue
-            u = mlp(_t(params[q]), prob.subdomains[q].widths, _t(xy[sel])).numpy()
+            sd = prob.subdomains[q]
+            thu, thk = split_theta(prob, q, _t(params[q]))
+            u = mlp(thu, sd.widths, _t(xy[sel])).numpy()
+            if inv:   # inverse problem: columns (u, K)
+                u = np.concatenate([u, mlp(thk, sd.aux_widths, _t(xy[sel])).numpy()], 1)
             out[sel] += u / cnt[sel][:, None]
     return out
 

@@ -50,11 +50,11 @@ class Subdomain:
     bnd_xy: np.ndarray      # (N_u, 2) float32 training (boundary/initial/data) points
     bnd_g: np.ndarray       # (N_u, D_o) float32 targets u^(i)
     params: np.ndarray      # flat float32, per layer W[out][in] row-major then b[out]
-    # second network (inverse problems only: the unknown coefficient K)
+    # second network (inverse problems only: the unknown coefficient K); its
+    # parameters follow the solution network's in `params`
     aux_widths: list | None = None
-    aux_params: np.ndarray | None = None
-    aux_xy: np.ndarray | None = None     # points with known K values
-    aux_g: np.ndarray | None = None
+    aux_xy: np.ndarray | None = None     # (N_K, 2) points with known K values
+    aux_g: np.ndarray | None = None      # (N_K, 1) K targets
 
 
 @dataclass
@@ -387,11 +387,157 @@ def c4_xpinn_kovasznay(seed=0, scale=1.0, re=40.0):
         (1.0, 1.0, 1.0, 1.0), 1e-3, (151, 201))
 
 
+def star_radius(theta, amp, phase, r0=0.3):
+    """r(theta) = r0 (1 + sum_{k=2..5} amp_k cos(k theta + phase_k))."""
+    r = np.ones_like(theta)
+    for i, k in enumerate(range(2, 6)):
+        r = r + amp[i] * np.cos(k * theta + phase[i])
+    return r0 * r
+
+
+def _in_star(xy, center, amp, phase):
+    d = xy - center[None, :]
+    return np.hypot(d[:, 0], d[:, 1]) < star_radius(np.arctan2(d[:, 1], d[:, 0]), amp, phase)
+
+
+def _nearest(xy, sites):
+    d2 = ((xy[:, None, :] - sites[None, :, :]) ** 2).sum(-1)
+    return np.argmin(d2, 1), d2
+
+
+def c5_xpinn_inverse_diffusion(seed=0, scale=1.0, n_cells=10):
+    """XPINN for the inverse steady diffusion problem div(K grad u) = f
+    (Eq. heq, Sec. 7.6): the conductivity K is a second network per subdomain,
+    known only on the outer boundary, while u is observed inside the domain.
+
+    Stands in for the US-map geometry: a seeded star-shaped domain
+    r(theta) = 0.3 (1 + sum_{k=2..5} a_k cos(k theta + phi_k)) around (0.5, 0.5),
+    a_k ~ U[-0.06, 0.06], cut into n_cells Voronoi cells (sites at least 0.08
+    apart).  Per cell: u-net and K-net widths from {20,40,60,80,100} and
+    3..6 hidden layers, drawn independently; U_int[1000,30000] residual
+    points.  200 points on each shared Voronoi edge; 500 interior
+    observations u + 1% noise; 400 outer-boundary points with u and K targets.
+    Fields: u = sin(pi x) sin(pi y), K = 1 + 0.5 sin(2 pi x) cos(2 pi y).
+    Subdomain.params holds [u-net | K-net] (canonical layout each)."""
+    g, p, w, nz = _streams(seed)
+    center = np.array([0.5, 0.5])
+    amp = g.uniform(-0.06, 0.06, 4)
+    phase = g.uniform(0.0, 2 * np.pi, 4)
+    rmax = 0.3 * (1 + 4 * 0.06)
+    lo, hi = center - rmax, center + rmax
+
+    def uniform_in_star(rng, n):
+        out = np.zeros((0, 2))
+        while out.shape[0] < n:
+            c = rng.uniform(lo, hi, (max(64, 2 * (n - out.shape[0])), 2))
+            out = np.concatenate([out, c[_in_star(c, center, amp, phase)]], 0)
+        return out[:n]
+
+    sites = np.zeros((0, 2))
+    while sites.shape[0] < n_cells:
+        c = uniform_in_star(g, 1)
+        if sites.shape[0] == 0 or np.min(np.hypot(*(sites - c).T)) >= 0.08:
+            sites = np.concatenate([sites, c], 0)
+    wch = [20, 40, 60, 80, 100]
+    uw, kw, nres = [], [], []
+    for q in range(n_cells):
+        uw.append([2] + [int(g.choice(wch))] * int(g.integers(3, 7)) + [1])
+        kw.append([2] + [int(g.choice(wch))] * int(g.integers(3, 7)) + [1])
+        nres.append(max(1, int(round(int(g.integers(1000, 30001)) * scale))))
+
+    # residual points: uniform in the star, kept by nearest site up to each quota
+    res = [np.zeros((0, 2)) for _ in range(n_cells)]
+    while any(res[q].shape[0] < nres[q] for q in range(n_cells)):
+        c = uniform_in_star(p, 20000)
+        own, _ = _nearest(c, sites)
+        for q in range(n_cells):
+            need = nres[q] - res[q].shape[0]
+            if need > 0:
+                res[q] = np.concatenate([res[q], c[own == q][:need]], 0)
+
+    # interfaces: pieces of the bisector of two sites that are closer to them
+    # than to any other site and inside the domain
+    n_i = max(1, int(round(200 * scale)))
+    tg = np.linspace(-1.0, 1.0, 20001)
+    ifaces = []
+    for a in range(n_cells):
+        for b in range(a + 1, n_cells):
+            m = 0.5 * (sites[a] + sites[b])
+            nrm = (sites[b] - sites[a]) / np.linalg.norm(sites[b] - sites[a])
+            d = np.array([-nrm[1], nrm[0]])
+
+            def valid(t):
+                pts = m[None, :] + t[:, None] * d[None, :]
+                own, d2 = _nearest(pts, sites)
+                da = d2[:, a]
+                others = np.delete(d2, [a, b], axis=1)
+                ok = _in_star(pts, center, amp, phase)
+                if others.shape[1]:
+                    ok &= (others > da[:, None]).all(1)
+                return ok, pts
+
+            ok, _ = valid(tg)
+            if ok.sum() < 50:          # no shared edge (or a sliver) inside the domain
+                continue
+            t_lo, t_hi = tg[ok].min(), tg[ok].max()
+            got = np.zeros((0, 2))
+            while got.shape[0] < n_i:
+                t = p.uniform(t_lo, t_hi, 2 * n_i)
+                okt, pts = valid(t)
+                got = np.concatenate([got, pts[okt]], 0)
+            ifaces.append(Interface(a, b, _f32(got[:n_i]), _f32(nrm)))
+
+    # data: interior observations of u with 1% noise, boundary u and K
+    n_obs = max(1, int(round(500 * scale)))
+    n_bd = max(1, int(round(400 * scale)))
+    obs = uniform_in_star(p, n_obs)
+    u_obs, _, _ = diffusion_fields(obs[:, 0], obs[:, 1])
+    u_obs = u_obs + 0.01 * np.std(u_obs) * nz.standard_normal(n_obs)
+    th = p.uniform(0.0, 2 * np.pi, n_bd)
+    rb = star_radius(th, amp, phase)
+    bd = center[None, :] + rb[:, None] * np.stack([np.cos(th), np.sin(th)], 1)
+    u_bd, k_bd, _ = diffusion_fields(bd[:, 0], bd[:, 1])
+    own_obs, _ = _nearest(obs, sites)
+    own_bd, _ = _nearest(bd, sites)
+
+    subs = []
+    for q in range(n_cells):
+        r = res[q]
+        _, _, f = diffusion_fields(r[:, 0], r[:, 1])
+        so, sb = own_obs == q, own_bd == q
+        dxy = np.concatenate([obs[so], bd[sb]], 0)
+        dg = np.concatenate([u_obs[so], u_bd[sb]], 0)[:, None]
+        pu, pk = glorot_params(w, uw[q]), glorot_params(w, kw[q])
+        subs.append(Subdomain(widths=uw[q], loss_w=(1.0, 1.0, 1.0, 1.0), lr=6e-3,
+                              res_xy=_f32(r), res_f=_f32(f[:, None]), bnd_xy=_f32(dxy), bnd_g=_f32(dg),
+                              params=np.concatenate([pu, pk]), aux_widths=kw[q],
+                              aux_xy=_f32(bd[sb]), aux_g=_f32(k_bd[sb][:, None])))
+    # evaluation grid inside the star; owners = nearest site(s)
+    gx = np.linspace(lo[0], hi[0], 201)
+    X, Y = np.meshgrid(gx, np.linspace(lo[1], hi[1], 201), indexing="ij")
+    exy = np.stack([X.ravel(), Y.ravel()], 1)
+    exy = _f32(exy[_in_star(exy, center, amp, phase)])
+    ex = exy.astype(np.float64)
+    _, d2 = _nearest(ex, sites)
+    dmin = d2.min(1, keepdims=True)
+    tie = d2 <= dmin * (1 + 1e-9)
+    owner = -np.ones((len(ex), 4), np.int32)
+    for i in range(len(ex)):
+        qs = np.nonzero(tie[i])[0][:4]
+        owner[i, :len(qs)] = qs
+    ue, ke, _ = diffusion_fields(ex[:, 0], ex[:, 1])
+    return Problem(name="c5_xpinn_inverse_diffusion", method=METHOD_XPINN, pde=PDE_DIFFUSION2D_INV,
+                   coef=(), subdomains=subs, interfaces=ifaces, eval_xy=exy, eval_owner=owner,
+                   eval_exact=np.stack([ue, ke], 1),
+                   meta={"sites": sites, "center": center, "amp": amp, "phase": phase})
+
+
 WORKLOADS = {
     "c1_cpinn_poisson": c1_cpinn_poisson,
     "c2_xpinn_poisson": c2_xpinn_poisson,
     "c3_cpinn_burgers": c3_cpinn_burgers,
     "c4_xpinn_kovasznay": c4_xpinn_kovasznay,
+    "c5_xpinn_inverse_diffusion": c5_xpinn_inverse_diffusion,
 }
 
 

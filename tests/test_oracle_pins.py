@@ -332,3 +332,147 @@ def test_burgers_reference_solution():
     np.testing.assert_allclose(u1, u2, atol=1e-8)
     # odd symmetry u(-x,t) = -u(x,t)
     np.testing.assert_allclose(W.burgers_exact(-xb, t, nu), -u1, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# inverse diffusion problem (Eq. heq): u-network and K-network per subdomain
+
+
+def _tiny_c5(seed=1, scale=0.01, wu=(2, 3, 3, 1), wk=(2, 4, 4, 1)):
+    """The config-5 geometry and point sets with tiny networks (gradient checks)."""
+    prob = W.c5_xpinn_inverse_diffusion(seed=seed, scale=scale)
+    rng = np.random.default_rng(seed + 100)
+    for s in prob.subdomains:
+        s.widths, s.aux_widths = list(wu), list(wk)
+        s.params = np.concatenate([W.glorot_params(rng, s.widths), W.glorot_params(rng, s.aux_widths)])
+    return prob
+
+
+def test_inverse_operator_vs_divergence_form_fd():
+    """K Lap u + grad K . grad u equals div(K grad u) evaluated by nested central
+    differences of the two networks (the form Eq. heq is written in)."""
+    rng = np.random.default_rng(7)
+    wu, wk = [2, 5, 5, 1], [2, 4, 6, 1]
+    thu, thk = _rand_theta(rng, wu), _rand_theta(rng, wk)
+    z = torch.tensor(rng.uniform(0.2, 0.8, (9, 2)), dtype=DT)
+    stu = O.input_streams(thu, wu, z, O.DIFF_INV, create_graph=False)
+    stk = O.input_streams(thk, wk, z, O.DIFF_INV, create_graph=False)
+    L = O.residual_inverse(stu, stk, torch.zeros((9, 1), dtype=DT))[:, 0]
+    U = lambda zz: O.mlp(thu, wu, zz)[:, 0].detach()
+    K = lambda zz: O.mlp(thk, wk, zz)[:, 0].detach()
+    hi, ho = 1e-5, 1e-3
+
+    def flux(zz, i):   # K du/dz_i by a central difference
+        e = torch.zeros(2, dtype=DT)
+        e[i] = hi
+        return K(zz) * (U(zz + e) - U(zz - e)) / (2 * hi)
+
+    div = torch.zeros(9, dtype=DT)
+    for i in range(2):
+        e = torch.zeros(2, dtype=DT)
+        e[i] = ho
+        div += (flux(z + e, i) - flux(z - e, i)) / (2 * ho)
+    np.testing.assert_allclose(L.numpy(), div.numpy(), rtol=2e-5, atol=2e-6)
+
+
+def test_inverse_exact_fields_zero_residual():
+    """The paper's fields T = 20 exp(-0.1 y), K = 20 + exp(0.1 y) sin(0.5 x) satisfy
+    Eq. heq with f = 4 exp(-0.1 y) (worked out by hand); the generator's
+    manufactured pair satisfies it with its own forcing."""
+    p = _pts(40, seed=11)
+    x, y = torch.tensor(p[:, 0], dtype=DT), torch.tensor(p[:, 1], dtype=DT)
+    e = torch.exp(-0.1 * y)
+    stu = {"u": (20 * e)[:, None], "du": torch.stack([0 * x, -2 * e], 1)[:, None, :],
+           "lap": (0.2 * e)[:, None]}
+    Kv = 20 + torch.sin(0.5 * x) / e
+    stk = {"u": Kv[:, None], "du": torch.stack([0.5 * torch.cos(0.5 * x) / e, 0.1 * torch.sin(0.5 * x) / e],
+                                               1)[:, None, :]}
+    F = O.residual_inverse(stu, stk, (4 * e)[:, None])
+    assert float(F.abs().max()) < 1e-12
+    # generator's pair: u = sin(pi x) sin(pi y), K = 1 + 0.5 sin(2 pi x) cos(2 pi y)
+    pi = math.pi
+    u = torch.sin(pi * x) * torch.sin(pi * y)
+    stu = {"u": u[:, None], "du": torch.stack([pi * torch.cos(pi * x) * torch.sin(pi * y),
+                                               pi * torch.sin(pi * x) * torch.cos(pi * y)], 1)[:, None, :],
+           "lap": (-2 * pi * pi * u)[:, None]}
+    stk = {"u": (1 + 0.5 * torch.sin(2 * pi * x) * torch.cos(2 * pi * y))[:, None],
+           "du": torch.stack([pi * torch.cos(2 * pi * x) * torch.cos(2 * pi * y),
+                              -pi * torch.sin(2 * pi * x) * torch.sin(2 * pi * y)], 1)[:, None, :]}
+    _, _, f = W.diffusion_fields(p[:, 0], p[:, 1])
+    F = O.residual_inverse(stu, stk, torch.tensor(f, dtype=DT)[:, None])
+    assert float(F.abs().max()) < 1e-11
+
+
+def test_inverse_zero_networks_closed_forms():
+    """u = K = 0: MSE_F = mean(f^2), MSE_u = mean(g_u^2) + mean(g_K^2) (0 for an
+    empty K set), interface terms 0."""
+    prob = W.c5_xpinn_inverse_diffusion(seed=0, scale=0.02)
+    params = [np.zeros_like(s.params) for s in prob.subdomains]
+    terms, _ = O.loss_and_grad(prob, params)
+    n_empty = 0
+    for q, s in enumerate(prob.subdomains):
+        f = s.res_f.astype(np.float64)[:, 0]
+        gu = s.bnd_g.astype(np.float64)[:, 0]
+        gk = s.aux_g.astype(np.float64)[:, 0]
+        ref = (np.mean(gu * gu) if gu.size else 0.0) + (np.mean(gk * gk) if gk.size else 0.0)
+        n_empty += gk.size == 0
+        assert terms[q, 2] == pytest.approx(np.mean(f * f), rel=1e-13)
+        assert terms[q, 1] == pytest.approx(ref, rel=1e-13, abs=1e-300)
+        assert terms[q, 3] == 0 and terms[q, 4] == 0
+    assert n_empty >= 1   # an interior cell has no K data
+
+
+def test_inverse_interface_terms():
+    """Identical (u, K) pairs on both sides of every interface give zero
+    interface terms; the u-average term counts both u and K jumps."""
+    prob = _tiny_c5(seed=2)
+    p0 = prob.subdomains[0].params
+    terms, _ = O.loss_and_grad(prob, [p0.copy() for _ in prob.subdomains])
+    assert np.all(terms[:, 3] == 0) and np.all(terms[:, 4] == 0)
+    params = [W.perturb_params(s.params, 5, 0.3) for s in prob.subdomains]
+    terms, _ = O.loss_and_grad(prob, params)
+    e = prob.interfaces[0]
+    a, b = prob.subdomains[e.a], prob.subdomains[e.b]
+    z = torch.tensor(e.xy, dtype=DT)
+    na = W.param_count(a.widths)
+    nb = W.param_count(b.widths)
+    ta, tb = torch.tensor(params[e.a], dtype=DT), torch.tensor(params[e.b], dtype=DT)
+    du = O.mlp(ta[:na], a.widths, z) - O.mlp(tb[:nb], b.widths, z)
+    dk = O.mlp(ta[na:], a.aux_widths, z) - O.mlp(tb[nb:], b.aux_widths, z)
+    own = float((du ** 2).mean() + (dk ** 2).mean()) / 4
+    others = 0.0
+    for e2 in prob.interfaces[1:]:
+        if e.a in (e2.a, e2.b):
+            q2 = e2.b if e2.a == e.a else e2.a
+            c = prob.subdomains[q2]
+            nc = W.param_count(c.widths)
+            tc = torch.tensor(params[q2], dtype=DT)
+            z2 = torch.tensor(e2.xy, dtype=DT)
+            d1 = O.mlp(ta[:na], a.widths, z2) - O.mlp(tc[:nc], c.widths, z2)
+            d2 = O.mlp(ta[na:], a.aux_widths, z2) - O.mlp(tc[nc:], c.aux_widths, z2)
+            others += float((d1 ** 2).mean() + (d2 ** 2).mean()) / 4
+    assert terms[e.a, 3] == pytest.approx(own + others, rel=1e-12)
+
+
+def test_inverse_gradient_vs_central_fd():
+    prob = _tiny_c5(seed=3, scale=0.008)
+    params = [W.perturb_params(s.params, 4, 0.3) for s in prob.subdomains]
+    _, grads = O.loss_and_grad(prob, params)
+    for q in (0, 3):
+        fd = _fd_grad(prob, params, q)
+        np.testing.assert_allclose(grads[q], fd, rtol=2e-6, atol=1e-8)
+        n_u = W.param_count(prob.subdomains[q].widths)
+        assert np.linalg.norm(grads[q][n_u:]) > 1e-6   # the K-network is trained too
+
+
+def test_inverse_local_gradient_vs_gradient_of_total():
+    prob = _tiny_c5(seed=4)
+    params = [W.perturb_params(s.params, 1, 0.2) for s in prob.subdomains]
+    _, g_local = O.loss_and_grad(prob, params)
+    g_total = O.grad_of_total(prob, params)
+    prob_i = _tiny_c5(seed=4)
+    for s in prob_i.subdomains:
+        s.loss_w = (0.0, 0.0, 1.0, 1.0)
+    _, g_iface = O.loss_and_grad(prob_i, params)
+    for q in range(prob.n_sd):
+        np.testing.assert_allclose(g_total[q], g_local[q] + g_iface[q], rtol=1e-10, atol=1e-13)
