@@ -53,14 +53,20 @@ enum {
 enum { DDP_CPINN = 0, DDP_XPINN = 1 };
 
 /* Operators L_x of Eq. ProSet (F = L_x(u) - f):
- *  POISSON2D    -Lap u = f, inputs (x, y), one output.
- *  BURGERS1D    u_t + u u_x - nu u_xx = f (Eq. BE), inputs (x, t), coef[0] = nu.
- *  NS2D_STEADY  steady incompressible Navier-Stokes (Eq. NSEq), inputs (x, y),
- *               outputs (u, v, p), coef[0] = Re; three residual equations. */
-enum { DDP_POISSON2D = 0, DDP_BURGERS1D = 1, DDP_NS2D_STEADY = 2 };
+ *  POISSON2D      -Lap u = f, inputs (x, y), one output.
+ *  BURGERS1D      u_t + u u_x - nu u_xx = f (Eq. BE), inputs (x, t), coef[0] = nu.
+ *  NS2D_STEADY    steady incompressible Navier-Stokes (Eq. NSEq), inputs (x, y),
+ *                 outputs (u, v, p), coef[0] = Re; three residual equations.
+ *  DIFFUSION2D_INV  inverse problem of Sec. 7.6, div(K grad u) = f (Eq. heq),
+ *                 inputs (x, y): every subdomain has two one-output networks,
+ *                 u and the unknown conductivity K; F = K Lap u + grad K . grad u
+ *                 - f.  XPINN only: the interface terms match the average of
+ *                 the pair (u, K) and the operator value L(u, K). */
+enum { DDP_POISSON2D = 0, DDP_BURGERS1D = 1, DDP_NS2D_STEADY = 2, DDP_DIFFUSION2D_INV = 3 };
 
-/* point kinds for ddp_set_points */
-enum { DDP_RESIDUAL = 0, DDP_DATA = 1 };
+/* point kinds for ddp_set_points; DATA_AUX = points with known K values
+ * (inverse problem), whose squared misfit is added to MSE_u */
+enum { DDP_RESIDUAL = 0, DDP_DATA = 1, DDP_DATA_AUX = 2 };
 
 /* tuning options (ddp_set_option), all optional */
 enum {
@@ -73,9 +79,13 @@ enum {
  * operator list above).  method is DDP_CPINN or DDP_XPINN. */
 int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n_coef);
 
-/* Add subdomain Omega_q with its network (Sec. 3).  n_nets must be 1.
- * n_layers[0] = L + 1 entries of widths = N_0..N_L with N_0 = 2, N_L = number
- * of PDE outputs, hidden widths equal and at most 112, 1..8 hidden layers.
+/* Add subdomain Omega_q with its network (Sec. 3).  n_nets is 1, or 2 for
+ * DDP_DIFFUSION2D_INV (the u-network, then the K-network).  For each network
+ * i, n_layers[i] = L + 1 entries of widths (concatenated over the networks)
+ * = N_0..N_L with N_0 = 2, N_L = number of PDE outputs (1 for the K-network),
+ * hidden widths equal and at most 112, 1..8 hidden layers.  The subdomain's
+ * flat parameter vector is the u-network's canonical parameters followed by
+ * the K-network's.
  * loss_w = (W_u, W_F, W_I, W_flux for cPINN | W_IF for XPINN) of Eq. cPINNLoss
  * / Eq. XPINNLoss.  lr is this subdomain's Adam learning rate.  *sd_id
  * receives q (0-based, in call order). */
@@ -83,8 +93,9 @@ int ddp_add_subdomain(ddp_problem* p, int n_nets, const int* n_layers, const int
                       const float* loss_w, float lr, int* sd_id);
 
 /* Set the residual points {x_F} (kind DDP_RESIDUAL; val = forcing f(x), n x
- * n_eq) or training points {x_u} (kind DDP_DATA; val = targets u^(i), n x
- * N_L) of subdomain sd.  xy is n x 2 interleaved.  Replaces earlier points of
+ * n_eq), training points {x_u} (kind DDP_DATA; val = targets u^(i), n x
+ * N_L) or K data points (kind DDP_DATA_AUX, inverse problem; val = K, n x 1)
+ * of subdomain sd.  xy is n x 2 interleaved.  Replaces earlier points of
  * that kind.  Non-finite values are rejected.  Valid before ddp_finalize. */
 int ddp_set_points(ddp_problem* p, int sd, int kind, int n, const float* xy, const float* val,
                    int on_device);
@@ -144,7 +155,8 @@ int ddp_set_state(ddp_problem* p, const float* m, const float* v, int64_t t);
 
 /* Stitched solution of Eq. FSol at n points (device xy, n x 2).  owner (device,
  * n x 4 int32, -1 padded) lists the subdomains whose closure holds each point;
- * the output (device, n x N_L) averages their networks (indicator 1/S). */
+ * the output (device, n x N_L; n x 2 = (u, K) for DDP_DIFFUSION2D_INV)
+ * averages their networks (indicator 1/S). */
 int ddp_eval(ddp_problem* p, int n, const float* xy, const int* owner, float* u_out);
 
 /* Wait for the stream; DDP_ENONFINITE if a loss since the last sync was not

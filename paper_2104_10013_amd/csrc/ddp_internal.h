@@ -11,8 +11,10 @@ constexpr int kWaves = 4;         // waves per workgroup
 constexpr int kTilePts = 16 * kWaves;  // points per tile: 16 per wave
 constexpr int kLossTerms = 4;     // MSE_u, MSE_F, MSE_uavg, MSE_flux|MSE_R
 
-enum Kind { KIND_RES = 0, KIND_DATA = 1, KIND_IFACE = 2 };
-enum Pde { PDE_POISSON = 0, PDE_BURGERS = 1, PDE_NS = 2 };
+// point classes of a work item; KIND_AUX = points with known values of the
+// second network (the conductivity K of the inverse diffusion problem)
+enum Kind { KIND_RES = 0, KIND_DATA = 1, KIND_IFACE = 2, KIND_AUX = 3 };
+enum Pde { PDE_POISSON = 0, PDE_BURGERS = 1, PDE_NS = 2, PDE_INV = 3 };
 enum Method { METHOD_CPINN = 0, METHOD_XPINN = 1 };
 
 // One network: widths 2 -> w (x depth) -> d_out.
@@ -27,12 +29,20 @@ enum Method { METHOD_CPINN = 0, METHOD_XPINN = 1 };
 // Gradient partial rows use the same order without the transposes and
 // without the row padding:  [WP][4], per hidden layer [WP][WP] + [WP],
 // [d_out][WP] + [4].
+//
+// A subdomain owns one network, or two for the inverse diffusion problem (the
+// solution u, then the conductivity K at the next index).  Networks are the
+// unit of parameters, gradient rows, reduction and Adam; subdomains the unit
+// of loss terms.
 struct NetDesc {
+  int sd;           // owning subdomain
+  int pair;         // index of the K-network trained with this u-network, else -1
   int width;        // hidden width w
   int depth;        // hidden layers D
   int d_out;        // outputs
   int wclass;       // padded width class (multiple of 16)
   int64_t poff;     // offset of the canonical parameters in the flat buffer
+                    // (a subdomain's networks are adjacent: [u | K])
   int n_params;
   int64_t koff;     // offset of the kernel-layout copy
   int ksize;        // floats of the kernel-layout copy
@@ -61,7 +71,7 @@ struct Layout {
 
 // One work item: a contiguous range of one point set evaluated by one network.
 struct Item {
-  int q;            // subdomain / network
+  int q;            // network (the u-network for a paired item)
   int kind;         // Kind
   int begin;        // first point in the kind's packed array
   int count;        // number of points
@@ -69,11 +79,13 @@ struct Item {
   int side;         // 0: q is interface side a, 1: side b
   int lrow;         // loss partial row
   float inv_n;      // 1 / size of the point set whose mean this item feeds
-  int64_t prow;     // gradient partial row offset (floats)
+  int64_t prow;     // gradient partial row offset (floats); a paired item's
+                    // row holds the u-network's part, then the K-network's
 };
 
 struct IfaceDesc {
-  int a, b;
+  int a, b;         // subdomains
+  int a_net, b_net; // their (u-)networks
   int begin, count; // range in the packed interface point array
   float nx, ny;
 };
@@ -90,6 +102,8 @@ struct KArgs {
   const float* dat_xy;
   const float* dat_g;     // d_out per point
   const float* if_xy;
+  const float* aux_xy;    // KIND_AUX points
+  const float* aux_g;     // 1 per point
   float* partial;         // gradient partial rows
   float* loss_part;       // kLossTerms per loss row
   float* scratch;         // per-workgroup activation stash
@@ -111,12 +125,14 @@ struct RArgs {
   const float* partial;
   const float* loss_part;
   const NetDesc* nets;
-  const int64_t* sd_poff;     // n_sd + 1 prefix of parameter offsets
-  const int* sd_row_ptr;      // n_sd + 1: CSR over subdomains of the partial rows
-  const int64_t* row_prow;    // per CSR row: gradient partial offset
-  const int* row_lrow;        // per CSR row: loss row
-  int n_sd;
-  int q_begin, q_end;         // subdomain range handled by this launch
+  const int64_t* net_poff;    // n_nets + 1 prefix of parameter offsets
+  const int* net_row_ptr;     // n_nets + 1: CSR over networks of the partial rows
+  const int64_t* row_prow;    // per CSR row: offset of that network's part of a row
+  const int* sd_net;          // n_sd + 1: first network of each subdomain
+  const int* sd_loss_ptr;     // n_sd + 1: CSR over subdomains of the loss rows
+  const int* loss_rows;       // per CSR entry: loss row
+  int net_begin, net_end;     // networks reduced (and updated) by this launch
+  int sd_begin, sd_end;       // subdomains whose loss terms this launch sums
   float* grad_out;            // gradient output or nullptr
   float* loss_out;            // n_sd x 5 or nullptr
   int* flags;                 // [0] non-finite loss seen

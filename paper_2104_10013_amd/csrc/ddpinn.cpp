@@ -40,10 +40,11 @@ int fail(int code, const std::string& msg) {
 
 struct HostSd {
   std::vector<int> widths;
+  std::vector<int> aux_widths;  // K-network (inverse problem), else empty
   float loss_w[4];
   float lr;
-  std::vector<float> res_xy, res_f, dat_xy, dat_g;
-  int n_res = 0, n_dat = 0;
+  std::vector<float> res_xy, res_f, dat_xy, dat_g, aux_xy, aux_g;
+  int n_res = 0, n_dat = 0, n_aux = 0;
 };
 
 struct HostIf {
@@ -82,17 +83,21 @@ struct ddp_problem {
   bool planned = false, finalized = false;
   int fused = 1;
   int wpmax = 16;
-  std::vector<NetDesc> nets;
-  std::vector<int64_t> sd_poff;  // n_sd + 1
+  std::vector<NetDesc> nets;     // a subdomain's networks are adjacent: u [, K]
+  std::vector<int> sd_net;       // n_sd + 1: first network of each subdomain
+  std::vector<int64_t> sd_poff;  // n_sd + 1: parameter offsets of subdomains
+  std::vector<int64_t> net_poff; // n_nets + 1: parameter offsets of networks
   int64_t kparam_floats = 0;
   int plan_slots = 512;          // workgroups the plan balances for
   std::vector<Item> titems;      // train items (fused: descending cost; plain: grouped by q)
   std::vector<int> t_begin;      // per q ranges (plain path), n_sd + 1
   std::vector<IfaceDesc> ifaces;
-  std::vector<int> sd_rows, sd_row_ptr, row_lrow;
+  // gradient rows: CSR over networks (item index and offset of the network's
+  // part); loss rows: CSR over subdomains
+  std::vector<int> net_row_ptr, net_row_item, sd_loss_ptr, loss_rows;
   std::vector<int64_t> row_prow;
   int64_t partial_floats = 0;
-  std::vector<float> h_res_xy, h_res_f, h_dat_xy, h_dat_g, h_if_xy;
+  std::vector<float> h_res_xy, h_res_f, h_dat_xy, h_dat_g, h_if_xy, h_aux_xy, h_aux_g;
 
   // device
   int device = 0;
@@ -107,10 +112,11 @@ struct ddp_problem {
   Item* d_titems = nullptr;
   IfaceDesc* d_ifaces = nullptr;
   float *d_res_xy = nullptr, *d_res_f = nullptr, *d_dat_xy = nullptr, *d_dat_g = nullptr;
-  float* d_if_xy = nullptr;
+  float *d_if_xy = nullptr, *d_aux_xy = nullptr, *d_aux_g = nullptr;
   float *d_partial = nullptr, *d_loss_part = nullptr, *d_scratch = nullptr, *d_loss = nullptr;
-  int64_t* d_sd_poff = nullptr;
-  int *d_sd_row_ptr = nullptr, *d_row_lrow = nullptr;
+  int64_t* d_net_poff = nullptr;
+  int* d_sd_net = nullptr;
+  int *d_net_row_ptr = nullptr, *d_sd_loss_ptr = nullptr, *d_loss_rows = nullptr;
   int64_t* d_row_prow = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -182,6 +188,15 @@ double item_cost(const NetDesc& nd, int count) {
   return (double)count * (1.0 + (nd.depth - 1) * wp * wp * 24.0 + 40.0 * wp);
 }
 
+// work of an item of network q: a paired inverse item also trains the K-network
+// and evaluates it once more for its streams (a forward is a third of a train)
+double item_cost(const std::vector<NetDesc>& nets, const Item& it) {
+  double c = item_cost(nets[it.q], it.count);
+  if (nets[it.q].pair >= 0 && (it.kind == KIND_RES || it.kind == KIND_IFACE))
+    c += item_cost(nets[nets[it.q].pair], it.count) * (4.0 / 3.0);
+  return c;
+}
+
 int build_plan(ddp_problem* p) {
   const int n_sd = (int)p->sds.size();
   if (n_sd == 0) return fail(DDP_EINVAL, "no subdomains");
@@ -189,30 +204,41 @@ int build_plan(ddp_problem* p) {
     if (f.a >= n_sd || f.b >= n_sd) return fail(DDP_EINVAL, "interface names an unknown subdomain");
   const int64_t chunk_max = std::max<int64_t>(kTilePts, (p->chunk_points + kTilePts - 1) / kTilePts * kTilePts);
 
-  // networks and parameter offsets
-  p->nets.assign(n_sd, NetDesc{});
+  // networks (u, then K for the inverse problem) and parameter offsets
+  p->nets.clear();
+  p->sd_net.assign(n_sd + 1, 0);
   p->sd_poff.assign(n_sd + 1, 0);
+  p->net_poff.assign(1, 0);
   p->kparam_floats = 0;
   p->wpmax = 16;
   for (int q = 0; q < n_sd; ++q) {
     const HostSd& s = p->sds[q];
-    NetDesc& nd = p->nets[q];
-    nd.width = s.widths[1];
-    nd.depth = (int)s.widths.size() - 2;
-    nd.d_out = s.widths.back();
-    nd.wclass = width_class(nd.width);
-    nd.poff = p->sd_poff[q];
-    nd.n_params = (int)net_param_count(s.widths);
-    const Layout L(nd.wclass, nd.depth, nd.d_out);
-    nd.koff = p->kparam_floats;
-    nd.ksize = L.k_size();
-    nd.gsize = L.g_size();
-    p->kparam_floats += nd.ksize;
-    for (int k = 0; k < 4; ++k) nd.loss_w[k] = s.loss_w[k];
-    nd.lr = s.lr;
-    p->sd_poff[q + 1] = p->sd_poff[q] + nd.n_params;
-    p->wpmax = std::max(p->wpmax, nd.wclass);
+    p->sd_net[q] = (int)p->nets.size();
+    for (int which = 0; which < (s.aux_widths.empty() ? 1 : 2); ++which) {
+      const std::vector<int>& wd = which == 0 ? s.widths : s.aux_widths;
+      NetDesc nd{};
+      nd.sd = q;
+      nd.pair = (which == 0 && !s.aux_widths.empty()) ? (int)p->nets.size() + 1 : -1;
+      nd.width = wd[1];
+      nd.depth = (int)wd.size() - 2;
+      nd.d_out = wd.back();
+      nd.wclass = width_class(nd.width);
+      nd.poff = p->net_poff.back();
+      nd.n_params = (int)net_param_count(wd);
+      const Layout L(nd.wclass, nd.depth, nd.d_out);
+      nd.koff = p->kparam_floats;
+      nd.ksize = L.k_size();
+      nd.gsize = L.g_size();
+      p->kparam_floats += nd.ksize;
+      for (int k = 0; k < 4; ++k) nd.loss_w[k] = s.loss_w[k];
+      nd.lr = s.lr;
+      p->net_poff.push_back(nd.poff + nd.n_params);
+      p->wpmax = std::max(p->wpmax, nd.wclass);
+      p->nets.push_back(nd);
+    }
+    p->sd_poff[q + 1] = p->net_poff.back();
   }
+  p->sd_net[n_sd] = (int)p->nets.size();
 
   // packed point arrays
   p->h_res_xy.clear();
@@ -220,7 +246,9 @@ int build_plan(ddp_problem* p) {
   p->h_dat_xy.clear();
   p->h_dat_g.clear();
   p->h_if_xy.clear();
-  std::vector<int> res_begin(n_sd), dat_begin(n_sd);
+  p->h_aux_xy.clear();
+  p->h_aux_g.clear();
+  std::vector<int> res_begin(n_sd), dat_begin(n_sd), aux_begin(n_sd);
   for (int q = 0; q < n_sd; ++q) {
     const HostSd& s = p->sds[q];
     res_begin[q] = (int)(p->h_res_xy.size() / 2);
@@ -229,12 +257,17 @@ int build_plan(ddp_problem* p) {
     dat_begin[q] = (int)(p->h_dat_xy.size() / 2);
     p->h_dat_xy.insert(p->h_dat_xy.end(), s.dat_xy.begin(), s.dat_xy.end());
     p->h_dat_g.insert(p->h_dat_g.end(), s.dat_g.begin(), s.dat_g.end());
+    aux_begin[q] = (int)(p->h_aux_xy.size() / 2);
+    p->h_aux_xy.insert(p->h_aux_xy.end(), s.aux_xy.begin(), s.aux_xy.end());
+    p->h_aux_g.insert(p->h_aux_g.end(), s.aux_g.begin(), s.aux_g.end());
   }
   p->ifaces.clear();
   for (const HostIf& f : p->ifs) {
     IfaceDesc d;
     d.a = f.a;
     d.b = f.b;
+    d.a_net = p->sd_net[f.a];
+    d.b_net = p->sd_net[f.b];
     d.begin = (int)(p->h_if_xy.size() / 2);
     d.count = f.n;
     d.nx = f.nx;
@@ -243,34 +276,42 @@ int build_plan(ddp_problem* p) {
     p->ifaces.push_back(d);
   }
 
-  // Work items per subdomain: residual, data and interface-side chunks.  The
-  // chunk length of each network is chosen so items carry similar work
-  // (about 1/4 of an even share per workgroup), between one 64-point tile
-  // and chunk_max points: cheap networks get long items, expensive ones short.
+  // Work items per subdomain: residual, data and interface-side chunks (and
+  // K-data chunks of the inverse problem, where residual and interface items
+  // train both networks).  The chunk length of each subdomain is chosen so
+  // items carry similar work (about 1/items_per_slot of an even share per
+  // workgroup), between one 64-point tile and chunk_max points: cheap networks
+  // get long items, expensive ones short.
+  auto point_cost = [&](int q) {
+    Item one{};
+    one.q = p->sd_net[q];
+    one.kind = KIND_RES;
+    one.count = 1;
+    return item_cost(p->nets, one);
+  };
   double total_cost = 0.0;
   for (int q = 0; q < n_sd; ++q) {
     const HostSd& s = p->sds[q];
-    int n_pts = s.n_res + s.n_dat;
+    int n_pts = s.n_res + s.n_dat + s.n_aux;
     for (const HostIf& f : p->ifs)
       if (f.a == q || f.b == q) n_pts += f.n;
-    total_cost += item_cost(p->nets[q], n_pts);
+    total_cost += point_cost(q) * n_pts;
   }
   const double target = total_cost / ((double)std::max(1, p->items_per_slot) * std::max(1, p->plan_slots));
   std::vector<int64_t> chunk_q(n_sd);
   for (int q = 0; q < n_sd; ++q) {
-    const double per_pt = item_cost(p->nets[q], 1);
-    int64_t c = (int64_t)(target / per_pt);
+    int64_t c = (int64_t)(target / point_cost(q));
     c = (c + kTilePts - 1) / kTilePts * kTilePts;
     chunk_q[q] = std::min(chunk_max, std::max<int64_t>(kTilePts, c));
   }
   std::vector<std::vector<Item>> per_q(n_sd);
-  auto add_chunks = [&](int q, int kind, int begin, int count, int iface, int side, float inv_n) {
+  auto add_chunks = [&](int q, int net, int kind, int begin, int count, int iface, int side, float inv_n) {
     // interface items are one tile: the neighbour's network is evaluated on
     // the same tile first
     const int64_t chunk = kind == KIND_IFACE ? kTilePts : chunk_q[q];
     for (int64_t c0 = 0; c0 < count; c0 += chunk) {
       Item it{};
-      it.q = q;
+      it.q = net;
       it.kind = kind;
       it.begin = begin + (int)c0;
       it.count = (int)std::min<int64_t>(chunk, count - c0);
@@ -282,60 +323,75 @@ int build_plan(ddp_problem* p) {
   };
   for (int q = 0; q < n_sd; ++q) {
     const HostSd& s = p->sds[q];
-    if (s.n_res > 0) add_chunks(q, KIND_RES, res_begin[q], s.n_res, -1, 0, 1.f / (float)s.n_res);
-    if (s.n_dat > 0) add_chunks(q, KIND_DATA, dat_begin[q], s.n_dat, -1, 0, 1.f / (float)s.n_dat);
+    const int u = p->sd_net[q];
+    if (s.n_res > 0) add_chunks(q, u, KIND_RES, res_begin[q], s.n_res, -1, 0, 1.f / (float)s.n_res);
+    if (s.n_dat > 0) add_chunks(q, u, KIND_DATA, dat_begin[q], s.n_dat, -1, 0, 1.f / (float)s.n_dat);
+    if (s.n_aux > 0) add_chunks(q, u + 1, KIND_AUX, aux_begin[q], s.n_aux, -1, 0, 1.f / (float)s.n_aux);
   }
   for (int e = 0; e < (int)p->ifaces.size(); ++e) {
     const IfaceDesc& d = p->ifaces[e];
     if (d.count <= 0) continue;
-    add_chunks(d.a, KIND_IFACE, d.begin, d.count, e, 0, 1.f / (float)d.count);
-    add_chunks(d.b, KIND_IFACE, d.begin, d.count, e, 1, 1.f / (float)d.count);
+    add_chunks(d.a, d.a_net, KIND_IFACE, d.begin, d.count, e, 0, 1.f / (float)d.count);
+    add_chunks(d.b, d.b_net, KIND_IFACE, d.begin, d.count, e, 1, 1.f / (float)d.count);
   }
 
   // train items: fused = one list in descending cost (largest first, a
   // greedy longest-processing-time order for the dynamic queue); plain =
   // grouped by subdomain so each launch takes one contiguous range
+  auto by_cost = [&](const Item& x, const Item& y) { return item_cost(p->nets, x) > item_cost(p->nets, y); };
   p->titems.clear();
   p->t_begin.assign(n_sd + 1, 0);
   for (int q = 0; q < n_sd; ++q) {
     p->t_begin[q] = (int)p->titems.size();
     std::vector<Item> v = per_q[q];
-    std::stable_sort(v.begin(), v.end(), [&](const Item& x, const Item& y) {
-      return item_cost(p->nets[x.q], x.count) > item_cost(p->nets[y.q], y.count);
-    });
+    std::stable_sort(v.begin(), v.end(), by_cost);
     p->titems.insert(p->titems.end(), v.begin(), v.end());
   }
   p->t_begin[n_sd] = (int)p->titems.size();
-  if (p->fused) {
-    std::stable_sort(p->titems.begin(), p->titems.end(), [&](const Item& x, const Item& y) {
-      return item_cost(p->nets[x.q], x.count) > item_cost(p->nets[y.q], y.count);
-    });
-  }
-  // partial rows and loss rows follow item order
+  if (p->fused) std::stable_sort(p->titems.begin(), p->titems.end(), by_cost);
+  // partial rows and loss rows follow item order; a paired item's row holds
+  // the u-network's part, then the K-network's
+  auto paired = [&](const Item& it) {
+    return p->nets[it.q].pair >= 0 && (it.kind == KIND_RES || it.kind == KIND_IFACE);
+  };
   int64_t off = 0;
   for (int i = 0; i < (int)p->titems.size(); ++i) {
     Item& it = p->titems[i];
     it.lrow = i;
     it.prow = off;
-    off += p->nets[it.q].gsize;
+    off += p->nets[it.q].gsize + (paired(it) ? p->nets[p->nets[it.q].pair].gsize : 0);
   }
   p->partial_floats = off;
-  // per subdomain row lists (ascending item index: a fixed summation order)
-  p->sd_row_ptr.assign(n_sd + 1, 0);
-  for (const Item& it : p->titems) p->sd_row_ptr[it.q + 1]++;
-  for (int q = 0; q < n_sd; ++q) p->sd_row_ptr[q + 1] += p->sd_row_ptr[q];
-  p->sd_rows.assign(p->titems.size(), 0);
-  {
-    std::vector<int> fill(p->sd_row_ptr.begin(), p->sd_row_ptr.end() - 1);
-    for (int i = 0; i < (int)p->titems.size(); ++i) p->sd_rows[fill[p->titems[i].q]++] = i;
+  // gradient row lists per network, loss row lists per subdomain (ascending
+  // item index: a fixed summation order)
+  const int n_nets = (int)p->nets.size();
+  p->net_row_ptr.assign(n_nets + 1, 0);
+  p->sd_loss_ptr.assign(n_sd + 1, 0);
+  for (const Item& it : p->titems) {
+    p->net_row_ptr[it.q + 1]++;
+    if (paired(it)) p->net_row_ptr[p->nets[it.q].pair + 1]++;
+    p->sd_loss_ptr[p->nets[it.q].sd + 1]++;
   }
-  // partial and loss row offsets in the same CSR order, so the reduction
-  // reads them without going through the item list
-  p->row_prow.resize(p->titems.size());
-  p->row_lrow.resize(p->titems.size());
-  for (size_t r = 0; r < p->sd_rows.size(); ++r) {
-    p->row_prow[r] = p->titems[p->sd_rows[r]].prow;
-    p->row_lrow[r] = p->titems[p->sd_rows[r]].lrow;
+  for (int n = 0; n < n_nets; ++n) p->net_row_ptr[n + 1] += p->net_row_ptr[n];
+  for (int q = 0; q < n_sd; ++q) p->sd_loss_ptr[q + 1] += p->sd_loss_ptr[q];
+  p->net_row_item.assign(p->net_row_ptr[n_nets], 0);
+  p->row_prow.assign(p->net_row_ptr[n_nets], 0);
+  p->loss_rows.assign(p->titems.size(), 0);
+  {
+    std::vector<int> fill(p->net_row_ptr.begin(), p->net_row_ptr.end() - 1);
+    std::vector<int> lfill(p->sd_loss_ptr.begin(), p->sd_loss_ptr.end() - 1);
+    for (int i = 0; i < (int)p->titems.size(); ++i) {
+      const Item& it = p->titems[i];
+      int r = fill[it.q]++;
+      p->net_row_item[r] = i;
+      p->row_prow[r] = it.prow;
+      if (paired(it)) {
+        r = fill[p->nets[it.q].pair]++;
+        p->net_row_item[r] = i;
+        p->row_prow[r] = it.prow + p->nets[it.q].gsize;
+      }
+      p->loss_rows[lfill[p->nets[it.q].sd]++] = it.lrow;
+    }
   }
   p->planned = true;
   return DDP_OK;
@@ -351,6 +407,8 @@ KArgs make_kargs(ddp_problem* p) {
   ka.dat_xy = p->d_dat_xy;
   ka.dat_g = p->d_dat_g;
   ka.if_xy = p->d_if_xy;
+  ka.aux_xy = p->d_aux_xy;
+  ka.aux_g = p->d_aux_g;
   ka.partial = p->d_partial;
   ka.loss_part = p->d_loss_part;
   ka.scratch = p->d_scratch;
@@ -371,14 +429,23 @@ RArgs make_rargs(ddp_problem* p) {
   ra.partial = p->d_partial;
   ra.loss_part = p->d_loss_part;
   ra.nets = p->d_nets;
-  ra.sd_poff = p->d_sd_poff;
-  ra.sd_row_ptr = p->d_sd_row_ptr;
+  ra.net_poff = p->d_net_poff;
+  ra.net_row_ptr = p->d_net_row_ptr;
   ra.row_prow = p->d_row_prow;
-  ra.row_lrow = p->d_row_lrow;
-  ra.n_sd = (int)p->sds.size();
+  ra.sd_net = p->d_sd_net;
+  ra.sd_loss_ptr = p->d_sd_loss_ptr;
+  ra.loss_rows = p->d_loss_rows;
   ra.flags = p->d_flags;
   ra.tstate = p->d_tstate;
   return ra;
+}
+
+// reduction of subdomains [q0, q1): their networks and their loss terms
+void reduce_range(ddp_problem* p, RArgs& ra, int q0, int q1) {
+  ra.net_begin = p->sd_net[q0];
+  ra.net_end = p->sd_net[q1];
+  ra.sd_begin = q0;
+  ra.sd_end = q1;
 }
 
 int reduce_grid(ddp_problem* p, int q0, int q1) {
@@ -398,8 +465,7 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
     HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, st));
     RArgs ra = make_rargs(p);
-    ra.q_begin = 0;
-    ra.q_end = n_sd;
+    reduce_range(p, ra, 0, n_sd);
     ra.grad_out = grad_out;
     ra.loss_out = loss_out;
     ra.do_adam = do_adam;
@@ -421,8 +487,7 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
   }
   for (int q = 0; q < n_sd; ++q) {
     RArgs ra = make_rargs(p);
-    ra.q_begin = q;
-    ra.q_end = q + 1;
+    reduce_range(p, ra, q, q + 1);
     ra.grad_out = grad_out;
     ra.loss_out = loss_out;
     ra.do_adam = do_adam;
@@ -476,7 +541,7 @@ int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n
   if (!out) return fail(DDP_EINVAL, "null output pointer");
   *out = nullptr;
   if (method != DDP_CPINN && method != DDP_XPINN) return fail(DDP_EINVAL, "method must be DDP_CPINN or DDP_XPINN");
-  if (pde < DDP_POISSON2D || pde > DDP_NS2D_STEADY) return fail(DDP_EINVAL, "unknown operator");
+  if (pde < DDP_POISSON2D || pde > DDP_DIFFUSION2D_INV) return fail(DDP_EINVAL, "unknown operator");
   if (n_coef < 0 || n_coef > 4 || (n_coef > 0 && !coef)) return fail(DDP_EINVAL, "bad coefficient array");
   if ((pde == DDP_BURGERS1D || pde == DDP_NS2D_STEADY) && n_coef < 1)
     return fail(DDP_EINVAL, "operator needs coef[0] (nu or Re)");
@@ -484,6 +549,8 @@ int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n
     if (!std::isfinite(coef[i]) || coef[i] <= 0) return fail(DDP_EINVAL, "coefficients must be finite and > 0");
   if (method == DDP_CPINN && pde == DDP_NS2D_STEADY)
     return fail(DDP_EINVAL, "cPINN flux terms are not provided for Navier-Stokes; use DDP_XPINN");
+  if (method == DDP_CPINN && pde == DDP_DIFFUSION2D_INV)
+    return fail(DDP_EINVAL, "the inverse diffusion problem uses XPINN interfaces");
   ddp_problem* p = new (std::nothrow) ddp_problem();
   if (!p) return fail(DDP_ENOMEM, "out of host memory");
   p->method = method;
@@ -495,25 +562,38 @@ int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n
   return DDP_OK;
 }
 
-int ddp_add_subdomain(ddp_problem* p, int n_nets, const int* n_layers, const int* widths, const float* loss_w,
-                      float lr, int* sd_id) {
-  if (int rc = check_open(p)) return rc;
-  if (n_nets != 1) return fail(DDP_EINVAL, "exactly one network per subdomain is supported");
-  if (!n_layers || !widths || !loss_w) return fail(DDP_EINVAL, "null argument");
-  const int nl = n_layers[0];
+namespace {
+int check_widths(const int* widths, int nl, int d_out) {
   if (nl < 3) return fail(DDP_EINVAL, "a network needs input, at least one hidden and an output layer");
   if (nl - 2 > kMaxDepth) return fail(DDP_EINVAL, "at most 8 hidden layers");
   if (widths[0] != 2) return fail(DDP_EINVAL, "input width must be 2");
-  if (widths[nl - 1] != p->d_out) return fail(DDP_EINVAL, "output width must equal the operator's outputs");
+  if (widths[nl - 1] != d_out) return fail(DDP_EINVAL, "output width must equal the operator's outputs");
   const int w = widths[1];
   if (w < 1 || w > kMaxWidth) return fail(DDP_EINVAL, "hidden width must be in [1, 112]");
   for (int k = 1; k < nl - 1; ++k)
     if (widths[k] != w) return fail(DDP_EINVAL, "hidden layers of one network must have equal widths");
+  return DDP_OK;
+}
+}  // namespace
+
+int ddp_add_subdomain(ddp_problem* p, int n_nets, const int* n_layers, const int* widths, const float* loss_w,
+                      float lr, int* sd_id) {
+  if (int rc = check_open(p)) return rc;
+  const int need = p->pde == DDP_DIFFUSION2D_INV ? 2 : 1;
+  if (n_nets != need)
+    return fail(DDP_EINVAL, need == 2 ? "the inverse diffusion problem needs two networks (u, K) per subdomain"
+                                      : "this operator takes one network per subdomain");
+  if (!n_layers || !widths || !loss_w) return fail(DDP_EINVAL, "null argument");
+  const int nl = n_layers[0];
+  if (int rc = check_widths(widths, nl, p->d_out)) return rc;
+  if (n_nets == 2)
+    if (int rc = check_widths(widths + nl, n_layers[1], 1)) return rc;
   for (int k = 0; k < 4; ++k)
     if (!std::isfinite(loss_w[k]) || loss_w[k] < 0) return fail(DDP_EINVAL, "loss weights must be finite and >= 0");
   if (!std::isfinite(lr) || lr <= 0) return fail(DDP_EINVAL, "learning rate must be finite and > 0");
   HostSd s;
   s.widths.assign(widths, widths + nl);
+  if (n_nets == 2) s.aux_widths.assign(widths + nl, widths + nl + n_layers[1]);
   for (int k = 0; k < 4; ++k) s.loss_w[k] = loss_w[k];
   s.lr = lr;
   p->sds.push_back(std::move(s));
@@ -525,10 +605,12 @@ int ddp_add_subdomain(ddp_problem* p, int n_nets, const int* n_layers, const int
 int ddp_set_points(ddp_problem* p, int sd, int kind, int n, const float* xy, const float* val, int on_device) {
   if (int rc = check_open(p)) return rc;
   if (sd < 0 || sd >= (int)p->sds.size()) return fail(DDP_EINVAL, "unknown subdomain");
-  if (kind != DDP_RESIDUAL && kind != DDP_DATA) return fail(DDP_EINVAL, "unknown point kind");
+  if (kind != DDP_RESIDUAL && kind != DDP_DATA && kind != DDP_DATA_AUX) return fail(DDP_EINVAL, "unknown point kind");
+  if (kind == DDP_DATA_AUX && p->pde != DDP_DIFFUSION2D_INV)
+    return fail(DDP_EINVAL, "DDP_DATA_AUX points belong to the inverse diffusion problem");
   if (n < 0) return fail(DDP_EINVAL, "negative point count");
   HostSd& s = p->sds[sd];
-  const int nv = kind == DDP_RESIDUAL ? p->n_eq : p->d_out;
+  const int nv = kind == DDP_RESIDUAL ? p->n_eq : (kind == DDP_DATA ? p->d_out : 1);
   std::vector<float> hxy, hval;
   if (int rc = copy_in(xy, (size_t)n * 2, on_device, hxy)) return rc;
   if (int rc = copy_in(val, (size_t)n * nv, on_device, hval)) return rc;
@@ -538,6 +620,10 @@ int ddp_set_points(ddp_problem* p, int sd, int kind, int n, const float* xy, con
     s.res_xy.swap(hxy);
     s.res_f.swap(hval);
     s.n_res = n;
+  } else if (kind == DDP_DATA_AUX) {
+    s.aux_xy.swap(hxy);
+    s.aux_g.swap(hval);
+    s.n_aux = n;
   } else {
     s.dat_xy.swap(hxy);
     s.dat_g.swap(hval);
@@ -624,9 +710,10 @@ int install_plan(ddp_problem* p) {
   if ((rc = plan_alloc(p, &p->d_partial, (size_t)p->partial_floats))) return rc;
   if ((rc = plan_alloc(p, &p->d_loss_part, p->titems.size() * kLossTerms))) return rc;
   if ((rc = plan_alloc(p, &p->d_scratch, (size_t)p->n_slots * p->slot_floats))) return rc;
-  if ((rc = plan_upload(p, &p->d_sd_row_ptr, p->sd_row_ptr))) return rc;
+  if ((rc = plan_upload(p, &p->d_net_row_ptr, p->net_row_ptr))) return rc;
   if ((rc = plan_upload(p, &p->d_row_prow, p->row_prow))) return rc;
-  if ((rc = plan_upload(p, &p->d_row_lrow, p->row_lrow))) return rc;
+  if ((rc = plan_upload(p, &p->d_sd_loss_ptr, p->sd_loss_ptr))) return rc;
+  if ((rc = plan_upload(p, &p->d_loss_rows, p->loss_rows))) return rc;
   HIP_TRY(hipMemset(p->d_partial, 0, (size_t)std::max<int64_t>(1, p->partial_floats) * sizeof(float)));
   HIP_TRY(hipMemset(p->d_loss_part, 0, std::max<size_t>(1, p->titems.size() * kLossTerms) * sizeof(float)));
   HIP_TRY(hipDeviceSynchronize());
@@ -664,8 +751,10 @@ uint64_t problem_signature(const ddp_problem* p) {
   mix((int64_t)p->sds.size());
   for (const HostSd& s : p->sds) {
     for (int w : s.widths) mix(w);
+    for (int w : s.aux_widths) mix(w);
     mix(s.n_res);
     mix(s.n_dat);
+    mix(s.n_aux);
   }
   for (const HostIf& f : p->ifs) {
     mix(f.a);
@@ -728,8 +817,11 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   if ((rc = dev_upload(p, &p->d_dat_xy, p->h_dat_xy))) return rc;
   if ((rc = dev_upload(p, &p->d_dat_g, p->h_dat_g))) return rc;
   if ((rc = dev_upload(p, &p->d_if_xy, p->h_if_xy))) return rc;
+  if ((rc = dev_upload(p, &p->d_aux_xy, p->h_aux_xy))) return rc;
+  if ((rc = dev_upload(p, &p->d_aux_g, p->h_aux_g))) return rc;
   if ((rc = dev_alloc(p, &p->d_loss, (size_t)n_sd * 5))) return rc;
-  if ((rc = dev_upload(p, &p->d_sd_poff, p->sd_poff))) return rc;
+  if ((rc = dev_upload(p, &p->d_net_poff, p->net_poff))) return rc;
+  if ((rc = dev_upload(p, &p->d_sd_net, p->sd_net))) return rc;
   if ((rc = install_plan(p))) return rc;
   p->finalized = true;
   return DDP_OK;
@@ -803,17 +895,19 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
 int ddp_param_count(const ddp_problem* p, int sd, int64_t* n) {
   if (!p || !n) return fail(DDP_EINVAL, "null argument");
   if (sd < 0 || sd >= (int)p->sds.size()) return fail(DDP_EINVAL, "unknown subdomain");
-  *n = net_param_count(p->sds[sd].widths);
+  const HostSd& s = p->sds[sd];
+  *n = net_param_count(s.widths) + (s.aux_widths.empty() ? 0 : net_param_count(s.aux_widths));
   return DDP_OK;
 }
 
 int ddp_set_params(ddp_problem* p, int sd, const float* flat, int on_device) {
   if (int rc = check_final(p)) return rc;
   if (sd < 0 || sd >= (int)p->sds.size() || !flat) return fail(DDP_EINVAL, "bad subdomain or null pointer");
-  const size_t n = (size_t)p->nets[sd].n_params;
+  const size_t n = (size_t)(p->sd_poff[sd + 1] - p->sd_poff[sd]);
   HIP_TRY(hipMemcpyAsync(p->d_params + p->sd_poff[sd], flat, n * sizeof(float),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(launch_pack(p->d_params, p->d_kparams, p->d_nets, p->d_sd_poff, sd, sd + 1, (int64_t)n, p->stream));
+  HIP_TRY(launch_pack(p->d_params, p->d_kparams, p->d_nets, p->d_net_poff, p->sd_net[sd], p->sd_net[sd + 1],
+                      (int64_t)n, p->stream));
   if (!on_device) HIP_TRY(hipStreamSynchronize(p->stream));
   return DDP_OK;
 }
@@ -821,7 +915,7 @@ int ddp_set_params(ddp_problem* p, int sd, const float* flat, int on_device) {
 int ddp_get_params(ddp_problem* p, int sd, float* flat, int on_device) {
   if (int rc = check_final(p)) return rc;
   if (sd < 0 || sd >= (int)p->sds.size() || !flat) return fail(DDP_EINVAL, "bad subdomain or null pointer");
-  const size_t n = (size_t)p->nets[sd].n_params;
+  const size_t n = (size_t)(p->sd_poff[sd + 1] - p->sd_poff[sd]);
   HIP_TRY(hipMemcpyAsync(flat, p->d_params + p->sd_poff[sd], n * sizeof(float),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
   if (!on_device) HIP_TRY(hipStreamSynchronize(p->stream));
@@ -878,7 +972,9 @@ int ddp_set_state(ddp_problem* p, const float* m, const float* v, int64_t t) {
 int ddp_eval(ddp_problem* p, int n, const float* xy, const int* owner, float* u_out) {
   if (int rc = check_final(p)) return rc;
   if (n < 0 || (n > 0 && (!xy || !owner || !u_out))) return fail(DDP_EINVAL, "bad evaluation arguments");
-  HIP_TRY(launch_eval(p->d_params, p->d_nets, (int)p->sds.size(), n, xy, owner, u_out, p->d_out, p->stream));
+  const int n_cols = p->d_out + (p->pde == DDP_DIFFUSION2D_INV ? 1 : 0);
+  HIP_TRY(launch_eval(p->d_params, p->d_nets, p->d_sd_net, (int)p->sds.size(), n, xy, owner, u_out, n_cols,
+                      p->stream));
   return DDP_OK;
 }
 
@@ -921,8 +1017,7 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
         }
       } else {
         RArgs ra = make_rargs(p);
-        ra.q_begin = 0;
-        ra.q_end = n_sd;
+        reduce_range(p, ra, 0, n_sd);
         ra.loss_out = p->d_loss;
         ra.do_adam = 0;
         HIP_TRY(launch_reduce(ra, reduce_grid(p, 0, n_sd), p->stream));
@@ -952,10 +1047,10 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   for (size_t q = 0; q < p->nets.size(); ++q) {
     const NetDesc& n = p->nets[q];
     std::fprintf(f,
-                 "%s{\"width\": %d, \"depth\": %d, \"d_out\": %d, \"wclass\": %d, \"poff\": %lld, "
-                 "\"n_params\": %d, \"koff\": %lld, \"ksize\": %d, \"gsize\": %d}",
-                 q ? ", " : "", n.width, n.depth, n.d_out, n.wclass, (long long)n.poff, n.n_params, (long long)n.koff,
-                 n.ksize, n.gsize);
+                 "%s{\"sd\": %d, \"pair\": %d, \"width\": %d, \"depth\": %d, \"d_out\": %d, \"wclass\": %d, "
+                 "\"poff\": %lld, \"n_params\": %d, \"koff\": %lld, \"ksize\": %d, \"gsize\": %d}",
+                 q ? ", " : "", n.sd, n.pair, n.width, n.depth, n.d_out, n.wclass, (long long)n.poff, n.n_params,
+                 (long long)n.koff, n.ksize, n.gsize);
   }
   std::fprintf(f, "],\n\"ifaces\": [");
   for (size_t e = 0; e < p->ifaces.size(); ++e) {
@@ -973,13 +1068,23 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   };
   items("train_items", p->titems);
   std::fprintf(f, "],\n");
-  json_ints(f, "sd_row_ptr", p->sd_row_ptr);
+  json_ints(f, "sd_net", p->sd_net);
   std::fprintf(f, ",\n");
-  json_ints(f, "sd_rows", p->sd_rows);
+  json_ints(f, "net_row_ptr", p->net_row_ptr);
+  std::fprintf(f, ",\n");
+  json_ints(f, "net_row_item", p->net_row_item);
+  std::fprintf(f, ",\n\"net_row_prow\": [");
+  for (size_t r = 0; r < p->row_prow.size(); ++r) std::fprintf(f, "%s%lld", r ? ", " : "", (long long)p->row_prow[r]);
+  std::fprintf(f, "],\n");
+  json_ints(f, "sd_loss_ptr", p->sd_loss_ptr);
+  std::fprintf(f, ",\n");
+  json_ints(f, "loss_rows", p->loss_rows);
   std::fprintf(f, ",\n");
   json_ints(f, "t_begin", p->t_begin);
-  std::fprintf(f, ",\n\"partial_floats\": %lld, \"n_res\": %zu, \"n_dat\": %zu, \"n_if\": %zu}\n",
-               (long long)p->partial_floats, p->h_res_xy.size() / 2, p->h_dat_xy.size() / 2, p->h_if_xy.size() / 2);
+  std::fprintf(f,
+               ",\n\"partial_floats\": %lld, \"n_res\": %zu, \"n_dat\": %zu, \"n_if\": %zu, \"n_aux\": %zu}\n",
+               (long long)p->partial_floats, p->h_res_xy.size() / 2, p->h_dat_xy.size() / 2, p->h_if_xy.size() / 2,
+               p->h_aux_xy.size() / 2);
   std::fclose(f);
   return DDP_OK;
 }

@@ -19,11 +19,11 @@ hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream
 hipError_t launch_reset_counter(int* c, hipStream_t st);
 // gradient reduction, loss reduction and optional Adam; re-arms ra.counter_reset
 hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st);
-// refresh the kernel-layout parameter copy of subdomains [q_begin, q_end)
-hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets, const int64_t* sd_poff,
-                       int q_begin, int q_end, int64_t n, hipStream_t st);
-// stitched evaluation
-hipError_t launch_eval(const float* params, const NetDesc* nets, int n_sd, int n, const float* xy, const int* owner,
-                       float* out, int d_out, hipStream_t st);
+// refresh the kernel-layout parameter copy of networks [n_begin, n_end)
+hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets, const int64_t* net_poff,
+                       int n_begin, int n_end, int64_t n, hipStream_t st);
+// stitched evaluation: n_cols outputs per point from each owner's networks
+hipError_t launch_eval(const float* params, const NetDesc* nets, const int* sd_net, int n_sd, int n, const float* xy,
+                       const int* owner, float* out, int n_cols, hipStream_t st);
 
 }  // namespace ddp

@@ -220,6 +220,24 @@ template <> struct Op<PDE_NS> {
   __device__ static void flux_adj(const float (&u)[DO][4], float, float, float, float, float (&)[DO][4]) {}
 };
 
+// inverse diffusion div(K grad u) = f: both networks carry the (x, y)
+// Laplacian stream set; the operator couples the u-network's streams with
+// the K-network's and is evaluated in the paired epilogue of Tile, not here
+template <> struct Op<PDE_INV> : Op<PDE_POISSON> {};
+
+// epilogue modes of a train tile
+enum {
+  EPI_OWN = 0,    // the item's own loss terms and output seeds
+  EPI_INV_U = 1,  // u-network of a paired inverse item: loss, u seeds, and the K seeds into LDS
+  EPI_SEED = 2    // K-network of a paired inverse item: output seeds read from LDS, no loss
+};
+// values_tile modes
+enum {
+  VAL_OWN = 0,     // interface values of the item's method (u, then flux.n or L(u))
+  VAL_STREAMS = 1, // output streams (value, d/dz0, d/dz1) of a one-output network
+  VAL_INV_NB = 2   // inverse problem, neighbour u-network: (u, K, L(u, K)) with K from LDS
+};
+
 // ---------------------------------------------------------------------------
 // Tile processor for one padded width class WP.
 //
@@ -427,18 +445,53 @@ struct Tile {
 
   // loss contributions and output seeds of one point (the derivative of the
   // item's share of J_q with respect to the output streams)
-  __device__ static void epilogue(const KArgs& ka, const Item& it, const NetDesc& nd, int pt, bool valid,
-                                  const float* nb, const float (&u)[DO][4], float (&ub)[DO][4],
-                                  float (&loss)[kLossTerms]) {
+  //
+  // EPI_INV_U: inv holds the K-network's streams (K, K_x, K_y) per tile point
+  // and nb the neighbour's (u, K, L) on interfaces; F = L - f with
+  // L = K Lap u + K_x u_x + K_y u_y (Eq. heq expanded), and kb receives the
+  // seeds of (K, K_x, K_y).  EPI_SEED: the seeds come from inv + 3 TP.
+  template <int MODE>
+  __device__ static void epilogue(const KArgs& ka, const Item& it, const NetDesc& nd, int pt, int tp, bool valid,
+                                  const float* nb, const float* inv, const float (&u)[DO][4], float (&ub)[DO][4],
+                                  float (&loss)[kLossTerms], float (&kb)[3]) {
 #pragma unroll
     for (int c = 0; c < DO; ++c)
 #pragma unroll
       for (int s = 0; s < 4; ++s) ub[c][s] = 0.f;
 #pragma unroll
     for (int t = 0; t < kLossTerms; ++t) loss[t] = 0.f;
+    kb[0] = kb[1] = kb[2] = 0.f;
     if (!valid) return;
     const float inv_n = it.inv_n;
     const int gp = it.begin + pt;
+    if constexpr (MODE == EPI_SEED) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) ub[0][s] = inv[3 * TP + 3 * tp + s];
+      return;
+    } else if constexpr (MODE == EPI_INV_U) {
+      const float K = inv[3 * tp], Kx = inv[3 * tp + 1], Ky = inv[3 * tp + 2];
+      const float L = fmaf(K, u[0][3], fmaf(Kx, u[0][1], Ky * u[0][2]));
+      float c;
+      if (it.kind == KIND_RES) {
+        const float F = L - ka.res_f[gp];
+        loss[1] += F * F;
+        c = 2.f * nd.loss_w[1] * F * inv_n;
+      } else {
+        const float dT = u[0][0] - nb[0], dK = K - nb[1], dL = L - nb[2];
+        loss[2] += 0.25f * (dT * dT + dK * dK);
+        ub[0][0] += 0.5f * nd.loss_w[2] * dT * inv_n;
+        kb[0] += 0.5f * nd.loss_w[2] * dK * inv_n;
+        loss[3] += dL * dL;
+        c = 2.f * nd.loss_w[3] * dL * inv_n;
+      }
+      ub[0][1] += c * Kx;
+      ub[0][2] += c * Ky;
+      ub[0][3] += c * K;
+      kb[0] += c * u[0][3];
+      kb[1] += c * u[0][1];
+      kb[2] += c * u[0][2];
+      return;
+    }
     if (it.kind == KIND_RES) {
       float F[NEQ];
       Op<PDE>::residual(u, ka.res_f + (int64_t)gp * ka.n_eq, ka.coef0, F);
@@ -449,14 +502,15 @@ struct Tile {
         c[e] = 2.f * nd.loss_w[1] * F[e] * inv_n;
       }
       Op<PDE>::residual_adj(u, c, ka.coef0, ub);
-    } else if (it.kind == KIND_DATA) {
+    } else if (it.kind == KIND_DATA || it.kind == KIND_AUX) {
+      const float* tg = it.kind == KIND_DATA ? ka.dat_g : ka.aux_g;
 #pragma unroll
       for (int c = 0; c < DO; ++c) {
-        const float d = u[c][0] - ka.dat_g[(int64_t)gp * DO + c];
+        const float d = u[c][0] - tg[(int64_t)gp * DO + c];
         loss[0] += d * d;
         ub[c][0] += 2.f * nd.loss_w[0] * d * inv_n;
       }
-    } else {
+    } else if constexpr (PDE != PDE_INV) {
       const IfaceDesc ifd = ka.ifaces[it.iface];
       float ov[DO + NEQ];
       own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
@@ -497,10 +551,19 @@ struct Tile {
   }
 
   // ------------------------------------------------------------------------
-  // forward only: the values this network contributes on the interface points
-  // of a one-tile item (u and flux.n or L_x(u)), written to LDS for the other
-  // side's loss -- the exchange of Algorithm 1 as an on-chip read
-  __device__ static void values_tile(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* sNb) {
+  // forward only, one tile starting at point t0 of the item, results written by
+  // the first lane group of each point to dst (stride 3, or DO + NEQ for
+  // VAL_OWN):
+  //  VAL_OWN      the values this network contributes on an interface (u, then
+  //               flux.n or L_x(u)) for the other side's loss -- the exchange of
+  //               Algorithm 1 as an on-chip read;
+  //  VAL_STREAMS  the output streams (value, d/dz0, d/dz1) of a one-output
+  //               network (the K-network of the inverse problem);
+  //  VAL_INV_NB   (u, K, L(u, K)) of a neighbour's u-network, with its K streams
+  //               read from kin.
+  template <int VMODE>
+  __device__ static void values_tile(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* dst,
+                                     const float* kin, int t0) {
     float* sW = lds;
     const int tid = item_tid();
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -508,18 +571,18 @@ struct Tile {
     const int tp = wave * 16 + pc;
     const Layout L(WP, nd.depth, DO);
     const float* K = ka.kparams + nd.koff;
-    const IfaceDesc ifd = ka.ifaces[it.iface];
-    const bool valid = tp < it.count;
-    const int gp = it.begin + tp;
-    const float x = valid ? ka.if_xy[2 * (int64_t)gp] : 0.f;
-    const float y = valid ? ka.if_xy[2 * (int64_t)gp + 1] : 0.f;
+    const float* xyv = it.kind == KIND_IFACE ? ka.if_xy : ka.res_xy;
+    const bool valid = t0 + tp < it.count;
+    const int gp = it.begin + t0 + tp;
+    const float x = valid ? xyv[2 * (int64_t)gp] : 0.f;
+    const float y = valid ? xyv[2 * (int64_t)gp + 1] : 0.f;
     Streams H;
     {
       Streams A;
       layer1(K, x, y, g, A);
       activate(A, H);
     }
-    const __amdgpu_buffer_rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(sNb, 0, 0, 0x00020000);  // unused
+    const __amdgpu_buffer_rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(lds, 0, 0, 0x00020000);  // unused
     for (int k = 2; k <= nd.depth; ++k) {
       __syncthreads();
       stage(sW, K + L.k_w(k), tid);
@@ -533,11 +596,21 @@ struct Tile {
     }
     float u[DO][4];
     out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
-    if (g == 0) {
+    if (g != 0) return;
+    if constexpr (VMODE == VAL_OWN) {
+      const IfaceDesc ifd = ka.ifaces[it.iface];
       float ov[DO + NEQ];
       own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
 #pragma unroll
-      for (int v = 0; v < DO + NEQ; ++v) sNb[tp * (DO + NEQ) + v] = ov[v];
+      for (int v = 0; v < DO + NEQ; ++v) dst[tp * (DO + NEQ) + v] = ov[v];
+    } else if constexpr (VMODE == VAL_STREAMS) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) dst[3 * tp + s] = u[0][s];
+    } else {
+      const float Kv = kin[3 * tp], Kx = kin[3 * tp + 1], Ky = kin[3 * tp + 2];
+      dst[3 * tp] = u[0][0];
+      dst[3 * tp + 1] = Kv;
+      dst[3 * tp + 2] = fmaf(Kv, u[0][3], fmaf(Kx, u[0][1], Ky * u[0][2]));
     }
   }
 
@@ -546,9 +619,13 @@ struct Tile {
   //
   // PREFETCH_A: load a^{k-1} during layer k of the reverse pass (and a^D while
   // the output layer runs) instead of at the top of each reverse layer.
-  template <bool PREFETCH_A>
+  // Tiles starting at t_lo .. t_hi - 1 (step TP) of the item; roff is the
+  // offset of this network's part in the item's gradient row; MODE selects the
+  // epilogue (sInv: the LDS exchange area of the inverse problem).
+  template <bool PREFETCH_A, int MODE>
   __device__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
-                                   float* slot, const float* sNb) {
+                                   float* slot, const float* sNb, float* sInv, int t_lo, int t_hi,
+                                   int roff) {
     float* sW = lds;
     float* sA = sW + WP * WS;
     float* sH = sA + WP * TPS;
@@ -558,12 +635,15 @@ struct Tile {
     const int D = nd.depth;
     const Layout L(WP, D, DO);
     const float* K = ka.kparams + nd.koff;
-    float* R = ka.partial + it.prow;
-    const float* xy = it.kind == KIND_RES ? ka.res_xy : (it.kind == KIND_DATA ? ka.dat_xy : ka.if_xy);
+    float* R = ka.partial + it.prow + roff;
+    const float* xy = it.kind == KIND_RES    ? ka.res_xy
+                      : it.kind == KIND_DATA ? ka.dat_xy
+                      : it.kind == KIND_AUX  ? ka.aux_xy
+                                             : ka.if_xy;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(slot, 0, (int)(ka.scratch_slot * sizeof(float)), 0x00020000);
 
-    for (int t0 = 0; t0 < it.count; t0 += TP) {
+    for (int t0 = t_lo; t0 < t_hi; t0 += TP) {
       // lane indices re-derived per tile (see item_tid)
       int tid = item_tid();
       int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -610,8 +690,8 @@ struct Tile {
       out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
 
       // ---- loss terms and output seeds
-      float ub[DO][4], loss[kLossTerms];
-      epilogue(ka, it, nd, pt, valid, sNb + tp * (DO + NEQ), u, ub, loss);
+      float ub[DO][4], loss[kLossTerms], kb[3];
+      epilogue<MODE>(ka, it, nd, pt, tp, valid, sNb + tp * (PDE == PDE_INV ? 3 : DO + NEQ), sInv, u, ub, loss, kb);
 #pragma unroll
       for (int t = 0; t < kLossTerms; ++t) {
         float v = g == 0 ? loss[t] : 0.f;
@@ -626,6 +706,10 @@ struct Tile {
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int c = 0; c < DO; ++c) sU[(s * 3 + c) * TP + tp] = ub[c][s];
+        if constexpr (MODE == EPI_INV_U) {
+#pragma unroll
+          for (int s = 0; s < 3; ++s) sInv[3 * TP + 3 * tp + s] = kb[s];
+        }
       }
 
       // ---- output layer adjoint: g^D = W^{LT} ubar; dW^L, db^L
@@ -684,7 +768,7 @@ struct Tile {
         if (t < DO * WP) R[L.g_out() + t] = accL[r];
       }
       if (tid < DO) R[L.g_bout() + tid] = accB;
-      if (tid < kLossTerms) {
+      if (MODE != EPI_SEED && tid < kLossTerms) {   // the u pass holds a paired item's loss
         float v = 0.f;
         for (int wv = 0; wv < kWaves; ++wv) v += sRed[wv * kLossTerms + tid];
         accum(ka.loss_part + (int64_t)it.lrow * kLossTerms + tid, v * it.inv_n, first);
@@ -838,16 +922,24 @@ struct Tile {
   // entry from a kernel built for classes up to WPMAX: the a^k prefetch costs
   // registers, so it is used for classes up to 48 in kernels that run two
   // waves per SIMD anyway because of a wider class
-  template <int WPMAX>
+  template <int WPMAX, int MODE>
   __device__ static void train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* slot,
-                               const float* sNb) {
-    run_train<(WP <= 48 && WPMAX >= 48)>(ka, it, nd, lds, slot, sNb);
+                               const float* sNb, float* sInv, int t_lo, int t_hi, int roff) {
+    run_train<(WP <= 48 && WPMAX >= 48), MODE>(ka, it, nd, lds, slot, sNb, sInv, t_lo, t_hi, roff);
   }
 };
 
+// LDS floats of a train kernel for classes up to WP: the tile buffers of
+// Tile<WP> (sW, sA, sH, sU, sX, sRed), then the neighbour values sNb (6 per
+// point), then for the inverse problem 9 per point: the own K streams, the K
+// seeds, the neighbour's K streams.
+template <int WP, int PDE>
+constexpr int lds_tile_floats() {
+  return WP * (WP + 4) + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms;
+}
 template <int WP, int PDE>
 constexpr int lds_train_floats() {
-  return WP * (WP + 4) + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms + 6 * TP;
+  return lds_tile_floats<WP, PDE>() + 6 * TP + (PDE == PDE_INV ? 9 * TP : 0);
 }
 
 // bytes of dynamic LDS the train kernel is launched with: the tile buffers and
@@ -859,33 +951,62 @@ constexpr int lds_train_bytes() {
 
 // Run one item: for an interface item first evaluate the neighbour's network
 // on the same tile (its width class may differ), then the item's own network.
+// A paired item of the inverse problem goes tile by tile: the neighbour's K-
+// and u-networks (interfaces), the own K-network's streams, the u-network's
+// train pass (loss, u seeds, K seeds), then the K-network's train pass.
 template <int WPMAX, int PDE>
 __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                          float* slot) {
-  float* sNb = lds + lds_train_floats<WPMAX, PDE>() - 6 * TP;
-#define DDP_CASE(WPV, CALL)                            \
-  case WPV:                                            \
-    if constexpr (WPV <= WPMAX) Tile<WPV, PDE>::CALL;  \
+  float* sNb = lds + lds_tile_floats<WPMAX, PDE>();
+  float* sInv = sNb + 6 * TP;
+#define DDP_CASE(WPV, ...)                                    \
+  case WPV:                                                   \
+    if constexpr (WPV <= WPMAX) Tile<WPV, PDE>::__VA_ARGS__;  \
     break;
-#define DDP_SWITCH(CLS, CALL) \
-  switch (CLS) {              \
-    DDP_CASE(16, CALL)        \
-    DDP_CASE(32, CALL)        \
-    DDP_CASE(48, CALL)        \
-    DDP_CASE(64, CALL)        \
-    DDP_CASE(80, CALL)        \
-    DDP_CASE(96, CALL)        \
-    DDP_CASE(112, CALL)       \
-    default: break;           \
+#define DDP_SWITCH(CLS, ...)     \
+  switch (CLS) {                 \
+    DDP_CASE(16, __VA_ARGS__)    \
+    DDP_CASE(32, __VA_ARGS__)    \
+    DDP_CASE(48, __VA_ARGS__)    \
+    DDP_CASE(64, __VA_ARGS__)    \
+    DDP_CASE(80, __VA_ARGS__)    \
+    DDP_CASE(96, __VA_ARGS__)    \
+    DDP_CASE(112, __VA_ARGS__)   \
+    default: break;              \
   }
-  if (it.kind == KIND_IFACE) {
+  if constexpr (PDE == PDE_INV) {
+    if (nd.pair >= 0 && (it.kind == KIND_RES || it.kind == KIND_IFACE)) {
+      const NetDesc ndk = ka.nets[nd.pair];
+      NetDesc nbu = nd, nbk = ndk;
+      if (it.kind == KIND_IFACE) {
+        const IfaceDesc ifd = ka.ifaces[it.iface];
+        nbu = ka.nets[it.side == 0 ? ifd.b_net : ifd.a_net];
+        nbk = ka.nets[nbu.pair];
+      }
+      for (int t0 = 0; t0 < it.count; t0 += TP) {
+        __syncthreads();
+        if (it.kind == KIND_IFACE) {
+          DDP_SWITCH(nbk.wclass, template values_tile<VAL_STREAMS>(ka, it, nbk, lds, sInv + 6 * TP, nullptr, t0))
+          __syncthreads();
+          DDP_SWITCH(nbu.wclass, template values_tile<VAL_INV_NB>(ka, it, nbu, lds, sNb, sInv + 6 * TP, t0))
+          __syncthreads();
+        }
+        DDP_SWITCH(ndk.wclass, template values_tile<VAL_STREAMS>(ka, it, ndk, lds, sInv, nullptr, t0))
+        __syncthreads();
+        DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_INV_U>(ka, it, nd, lds, slot, sNb, sInv, t0, t0 + 1, 0))
+        DDP_SWITCH(ndk.wclass,
+                   template train<WPMAX, EPI_SEED>(ka, it, ndk, lds, slot, sNb, sInv, t0, t0 + 1, nd.gsize))
+      }
+      return;
+    }
+  } else if (it.kind == KIND_IFACE) {
     const IfaceDesc ifd = ka.ifaces[it.iface];
-    const NetDesc ndn = ka.nets[it.side == 0 ? ifd.b : ifd.a];
+    const NetDesc ndn = ka.nets[it.side == 0 ? ifd.b_net : ifd.a_net];
     __syncthreads();
-    DDP_SWITCH(ndn.wclass, values_tile(ka, it, ndn, lds, sNb))
+    DDP_SWITCH(ndn.wclass, template values_tile<VAL_OWN>(ka, it, ndn, lds, sNb, nullptr, 0))
     __syncthreads();
   }
-  DDP_SWITCH(nd.wclass, template train<WPMAX>(ka, it, nd, lds, slot, sNb))
+  DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_OWN>(ka, it, nd, lds, slot, sNb, sInv, 0, it.count, 0))
 #undef DDP_SWITCH
 #undef DDP_CASE
 }
@@ -970,15 +1091,16 @@ __device__ __forceinline__ void param_map(const NetDesc& nd, int li, int& g, int
   }
 }
 
-__device__ __forceinline__ int find_sd(const int64_t* sd_poff, int q, int64_t i) {
-  while (sd_poff[q + 1] <= i) ++q;
-  return q;
+// network holding flat parameter i, searching upward from network n
+__device__ __forceinline__ int find_net(const int64_t* net_poff, int n, int64_t i) {
+  while (net_poff[n + 1] <= i) ++n;
+  return n;
 }
 
-// Sum each subdomain's gradient partial rows in a fixed order, then write the
+// Sum each network's gradient partial rows in a fixed order, then write the
 // gradient and/or apply Adam (Kingma-Ba, bias corrected) and refresh the
-// kernel-layout copy; the waves of block 0 also sum the loss rows and flag
-// non-finite losses.
+// kernel-layout copy; the waves of block 0 also sum each subdomain's loss
+// rows and flag non-finite losses.
 //
 // A thread owns one parameter and keeps kRedLanes independent partial sums over
 // the rows (row r goes to sum r mod kRedLanes), combined by a fixed tree: the
@@ -986,18 +1108,18 @@ __device__ __forceinline__ int find_sd(const int64_t* sd_poff, int q, int64_t i)
 constexpr int kRedLanes = 16;
 
 __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
-  const int64_t p0 = ra.sd_poff[ra.q_begin], p1 = ra.sd_poff[ra.q_end];
+  const int64_t p0 = ra.net_poff[ra.net_begin], p1 = ra.net_poff[ra.net_end];
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   const float tstep = (float)(ra.tstate[0] + 1);
   const float bc1 = 1.f - powf(b1, tstep);
   const float bc2 = 1.f - powf(b2, tstep);
   for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int q = find_sd(ra.sd_poff, ra.q_begin, i);
+    const int q = find_net(ra.net_poff, ra.net_begin, i);
     const NetDesc nd = ra.nets[q];
     int gi, k1, k2;
-    param_map(nd, (int)(i - ra.sd_poff[q]), gi, k1, k2);
-    const int r0 = ra.sd_row_ptr[q], n = ra.sd_row_ptr[q + 1] - r0;
+    param_map(nd, (int)(i - ra.net_poff[q]), gi, k1, k2);
+    const int r0 = ra.net_row_ptr[q], n = ra.net_row_ptr[q + 1] - r0;
     const int64_t* pr = ra.row_prow + r0;
     const float* P = ra.partial + gi;
     float a[kRedLanes];
@@ -1035,16 +1157,16 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
     // one wave per subdomain: lane l sums rows l, l + 64, ...; then a fixed
     // butterfly across the wave
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q = ra.q_begin + wave; q < ra.q_end; q += (int)(blockDim.x >> 6)) {
+    for (int q = ra.sd_begin + wave; q < ra.sd_end; q += (int)(blockDim.x >> 6)) {
       float t[kLossTerms] = {0.f, 0.f, 0.f, 0.f};
-      for (int r = ra.sd_row_ptr[q] + lane; r < ra.sd_row_ptr[q + 1]; r += 64) {
-        const float* lp = ra.loss_part + (int64_t)ra.row_lrow[r] * kLossTerms;
+      for (int r = ra.sd_loss_ptr[q] + lane; r < ra.sd_loss_ptr[q + 1]; r += 64) {
+        const float* lp = ra.loss_part + (int64_t)ra.loss_rows[r] * kLossTerms;
         for (int k = 0; k < kLossTerms; ++k) t[k] += lp[k];
       }
       for (int k = 0; k < kLossTerms; ++k)
         for (int m = 32; m >= 1; m >>= 1) t[k] += __shfl_xor(t[k], m);
       if (lane == 0) {
-        const NetDesc nd = ra.nets[q];
+        const NetDesc nd = ra.nets[ra.sd_net[q]];
         float J = 0.f;
         for (int k = 0; k < kLossTerms; ++k) J += nd.loss_w[k] * t[k];
         if (ra.loss_out) {
@@ -1062,57 +1184,62 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
 
 __global__ void k_reset_counter(int* c) { *c = 0; }
 
-// Rewrite the kernel-layout copy of subdomains [q_begin, q_end) from their
+// Rewrite the kernel-layout copy of networks [n_begin, n_end) from their
 // canonical parameters (after the caller sets them).
 __global__ __launch_bounds__(256) void k_pack(const float* params, float* kparams, const NetDesc* nets,
-                                              const int64_t* sd_poff, int q_begin, int q_end) {
-  const int64_t p0 = sd_poff[q_begin], p1 = sd_poff[q_end];
+                                              const int64_t* net_poff, int n_begin, int n_end) {
+  const int64_t p0 = net_poff[n_begin], p1 = net_poff[n_end];
   for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int q = find_sd(sd_poff, q_begin, i);
+    const int q = find_net(net_poff, n_begin, i);
     const NetDesc nd = nets[q];
     int gi, k1, k2;
-    param_map(nd, (int)(i - sd_poff[q]), gi, k1, k2);
+    param_map(nd, (int)(i - net_poff[q]), gi, k1, k2);
     float* K = kparams + nd.koff;
     K[k1] = params[i];
     if (k2 >= 0) K[k2] = params[i];
   }
 }
 
-// Stitched solution (Eq. FSol): average of the owning networks' outputs.
-__global__ __launch_bounds__(256) void k_eval(const float* params, const NetDesc* nets, int n_sd, int n,
-                                              const float* xy, const int* owner, float* out, int d_out) {
+// Stitched solution (Eq. FSol): average of the owning subdomains' outputs;
+// the columns are the outputs of a subdomain's networks in order (u, or u
+// then K for the inverse problem).  One thread per point.
+__global__ __launch_bounds__(256) void k_eval(const float* params, const NetDesc* nets, const int* sd_net, int n_sd,
+                                              int n, const float* xy, const int* owner, float* out, int n_cols) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float acc[kMaxOut] = {0.f, 0.f, 0.f};
   int cnt = 0;
   float h[kMaxWidth], h2[kMaxWidth];
+  const float x = xy[2 * i], y = xy[2 * i + 1];
   for (int o = 0; o < 4; ++o) {
     const int q = owner[4 * i + o];
     if (q < 0 || q >= n_sd) continue;
     ++cnt;
-    const NetDesc nd = nets[q];
-    const float* P = params + nd.poff;
-    const int w = nd.width;
-    const float x = xy[2 * i], y = xy[2 * i + 1];
-    for (int m = 0; m < w; ++m) h[m] = tanhf(fmaf(P[2 * m], x, fmaf(P[2 * m + 1], y, P[2 * w + m])));
-    int64_t off = 3 * w;
-    for (int k = 2; k <= nd.depth; ++k) {
-      for (int m = 0; m < w; ++m) {
-        float a = P[off + w * w + m];
-        for (int j = 0; j < w; ++j) a = fmaf(P[off + m * w + j], h[j], a);
-        h2[m] = tanhf(a);
+    int col = 0;
+    for (int net = sd_net[q]; net < sd_net[q + 1]; ++net) {
+      const NetDesc nd = nets[net];
+      const float* P = params + nd.poff;
+      const int w = nd.width;
+      for (int m = 0; m < w; ++m) h[m] = tanhf(fmaf(P[2 * m], x, fmaf(P[2 * m + 1], y, P[2 * w + m])));
+      int64_t off = 3 * w;
+      for (int k = 2; k <= nd.depth; ++k) {
+        for (int m = 0; m < w; ++m) {
+          float a = P[off + w * w + m];
+          for (int j = 0; j < w; ++j) a = fmaf(P[off + m * w + j], h[j], a);
+          h2[m] = tanhf(a);
+        }
+        for (int m = 0; m < w; ++m) h[m] = h2[m];
+        off += w * w + w;
       }
-      for (int m = 0; m < w; ++m) h[m] = h2[m];
-      off += w * w + w;
-    }
-    for (int c = 0; c < nd.d_out; ++c) {
-      float a = P[off + nd.d_out * w + c];
-      for (int j = 0; j < w; ++j) a = fmaf(P[off + c * w + j], h[j], a);
-      acc[c] += a;
+      for (int c = 0; c < nd.d_out && col < n_cols; ++c, ++col) {
+        float a = P[off + nd.d_out * w + c];
+        for (int j = 0; j < w; ++j) a = fmaf(P[off + c * w + j], h[j], a);
+        acc[col] += a;
+      }
     }
   }
-  for (int c = 0; c < d_out; ++c) out[(int64_t)i * d_out + c] = cnt ? acc[c] / cnt : 0.f;
+  for (int c = 0; c < n_cols; ++c) out[(int64_t)i * n_cols + c] = cnt ? acc[c] / cnt : 0.f;
 }
 
 #ifndef DDP_KERNELS_ONLY
@@ -1149,6 +1276,7 @@ struct KTable {
 DDP_ROW(PDE_POISSON)
 DDP_ROW(PDE_BURGERS)
 DDP_ROW(PDE_NS)
+DDP_ROW(PDE_INV)
 #undef DDP_ROW
 
 static const void* pick(int pde, int wpmax) {
@@ -1158,6 +1286,7 @@ static const void* pick(int pde, int wpmax) {
     case PDE_POISSON: return KTable<PDE_POISSON>::train[c];
     case PDE_BURGERS: return KTable<PDE_BURGERS>::train[c];
     case PDE_NS: return KTable<PDE_NS>::train[c];
+    case PDE_INV: return KTable<PDE_INV>::train[c];
   }
   return nullptr;
 }
@@ -1170,6 +1299,7 @@ size_t lds_bytes(int pde, int wpmax) {
     case PDE_POISSON: f = KTable<PDE_POISSON>::lds[c]; break;
     case PDE_BURGERS: f = KTable<PDE_BURGERS>::lds[c]; break;
     case PDE_NS: f = KTable<PDE_NS>::lds[c]; break;
+    case PDE_INV: f = KTable<PDE_INV>::lds[c]; break;
   }
   return (size_t)f;
 }
@@ -1206,18 +1336,19 @@ hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets, const int64_t* sd_poff,
-                       int q_begin, int q_end, int64_t n, hipStream_t st) {
+hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets, const int64_t* net_poff,
+                       int n_begin, int n_end, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, params, kparams, nets, sd_poff, q_begin, q_end);
+  hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, params, kparams, nets, net_poff, n_begin, n_end);
   return hipGetLastError();
 }
 
-hipError_t launch_eval(const float* params, const NetDesc* nets, int n_sd, int n, const float* xy, const int* owner,
-                       float* out, int d_out, hipStream_t st) {
+hipError_t launch_eval(const float* params, const NetDesc* nets, const int* sd_net, int n_sd, int n, const float* xy,
+                       const int* owner, float* out, int n_cols, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eval, dim3((n + 255) / 256), dim3(256), 0, st, params, nets, n_sd, n, xy, owner, out, d_out);
+  hipLaunchKernelGGL(k_eval, dim3((n + 255) / 256), dim3(256), 0, st, params, nets, sd_net, n_sd, n, xy, owner, out,
+                     n_cols);
   return hipGetLastError();
 }
 

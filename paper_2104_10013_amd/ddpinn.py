@@ -19,8 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libddpinn.so")
 
 DDP_OK, DDP_EINVAL, DDP_ENOMEM, DDP_EHIP, DDP_ESTATE, DDP_ENONFINITE = 0, -1, -2, -3, -4, -5
 DDP_CPINN, DDP_XPINN = 0, 1
-DDP_POISSON2D, DDP_BURGERS1D, DDP_NS2D_STEADY = 0, 1, 2
-DDP_RESIDUAL, DDP_DATA = 0, 1
+DDP_POISSON2D, DDP_BURGERS1D, DDP_NS2D_STEADY, DDP_DIFFUSION2D_INV = 0, 1, 2, 3
+DDP_RESIDUAL, DDP_DATA, DDP_DATA_AUX = 0, 1, 2
 DDP_OPT_CHUNK_POINTS, DDP_OPT_BLOCKS_PER_CU, DDP_OPT_ITEMS_PER_SLOT = 0, 1, 2
 
 EXPORTED = [
@@ -31,7 +31,8 @@ EXPORTED = [
 ]
 
 _METHOD = {W.METHOD_CPINN: DDP_CPINN, W.METHOD_XPINN: DDP_XPINN}
-_PDE = {W.PDE_POISSON2D: DDP_POISSON2D, W.PDE_BURGERS1D: DDP_BURGERS1D, W.PDE_NS2D: DDP_NS2D_STEADY}
+_PDE = {W.PDE_POISSON2D: DDP_POISSON2D, W.PDE_BURGERS1D: DDP_BURGERS1D, W.PDE_NS2D: DDP_NS2D_STEADY,
+        W.PDE_DIFFUSION2D_INV: DDP_DIFFUSION2D_INV}
 
 _lib = None
 
@@ -113,20 +114,27 @@ class Problem:
         self.fused = bool(fused)
         self.n_sd = prob.n_sd
         self.d_out = prob.d_out
+        # columns of eval(): the inverse problem stitches (u, K)
+        self.n_eval_cols = prob.d_out + (1 if prob.pde == W.PDE_DIFFUSION2D_INV else 0)
         self._h = ctypes.c_void_p()
         coef = (ctypes.c_double * 4)(*([float(c) for c in prob.coef] + [0.0] * (4 - len(prob.coef))))
         _check(L.ddp_create(ctypes.byref(self._h), _METHOD[prob.method], _PDE[prob.pde], coef, len(prob.coef)))
         try:
             for s in prob.subdomains:
-                wd = (ctypes.c_int * len(s.widths))(*s.widths)
-                nl = (ctypes.c_int * 1)(len(s.widths))
+                nets = [s.widths] + ([s.aux_widths] if s.aux_widths is not None else [])
+                allw = [w for n in nets for w in n]
+                wd = (ctypes.c_int * len(allw))(*allw)
+                nl = (ctypes.c_int * len(nets))(*[len(n) for n in nets])
                 lw = (ctypes.c_float * 4)(*s.loss_w)
                 sid = ctypes.c_int()
-                _check(L.ddp_add_subdomain(self._h, 1, nl, wd, lw, float(s.lr), ctypes.byref(sid)))
+                _check(L.ddp_add_subdomain(self._h, len(nets), nl, wd, lw, float(s.lr), ctypes.byref(sid)))
                 rx, rf = _host_f32(s.res_xy), _host_f32(s.res_f)
                 _check(L.ddp_set_points(self._h, sid.value, DDP_RESIDUAL, rx.shape[0], _ptr(rx), _ptr(rf), 0))
                 bx, bg = _host_f32(s.bnd_xy), _host_f32(s.bnd_g)
                 _check(L.ddp_set_points(self._h, sid.value, DDP_DATA, bx.shape[0], _ptr(bx), _ptr(bg), 0))
+                if s.aux_widths is not None:
+                    ax, ag = _host_f32(s.aux_xy), _host_f32(s.aux_g)
+                    _check(L.ddp_set_points(self._h, sid.value, DDP_DATA_AUX, ax.shape[0], _ptr(ax), _ptr(ag), 0))
             for e in prob.interfaces:
                 xy = _host_f32(e.xy)
                 nrm = (ctypes.c_float * 2)(*[float(v) for v in e.normal])
@@ -215,7 +223,7 @@ class Problem:
     def eval(self, xy, owner):
         xy = torch.as_tensor(np.asarray(xy, np.float32), device=self.device).contiguous()
         ow = torch.as_tensor(np.asarray(owner, np.int32), device=self.device).contiguous()
-        out = torch.empty(xy.shape[0], self.d_out, dtype=torch.float32, device=self.device)
+        out = torch.empty(xy.shape[0], self.n_eval_cols, dtype=torch.float32, device=self.device)
         _check(_lib.ddp_eval(self._h, xy.shape[0], _ptr(xy), _ptr(ow), _ptr(out)))
         return out
 

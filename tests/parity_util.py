@@ -9,14 +9,17 @@ LOSS_RTOL = 1e-5
 GRAD_RTOL = 1e-5
 
 
-def layer_slices(widths):
+def layer_slices(widths, aux_widths=None):
+    """Slices of every weight matrix and bias vector in a subdomain's flat
+    parameters (the u-network, then the K-network of the inverse problem)."""
     out, off = [], 0
-    for k in range(1, len(widths)):
-        n = widths[k] * widths[k - 1]
-        out.append(slice(off, off + n))
-        off += n
-        out.append(slice(off, off + widths[k]))
-        off += widths[k]
+    for wd in [widths] + ([aux_widths] if aux_widths is not None else []):
+        for k in range(1, len(wd)):
+            n = wd[k] * wd[k - 1]
+            out.append(slice(off, off + n))
+            off += n
+            out.append(slice(off, off + wd[k]))
+            off += wd[k]
     return out
 
 
@@ -40,7 +43,8 @@ def compare(prob, params, lt_gpu, g_gpu, loss_rtol=LOSS_RTOL, grad_rtol=GRAD_RTO
         worst_g = max(worst_g, err)
         assert err <= grad_rtol, f"sd {q} grad rel {err:.3e} (|g|={nref:.3e})"
         if per_layer:
-            for k, sl in enumerate(layer_slices(prob.subdomains[q].widths)):
+            sd = prob.subdomains[q]
+            for k, sl in enumerate(layer_slices(sd.widths, sd.aux_widths)):
                 r = ref[sl]
                 nr = np.linalg.norm(r)
                 if nr < 1e-6 * nref:

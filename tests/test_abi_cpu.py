@@ -35,15 +35,24 @@ def _plan(prob, tmp_path, **kw):
     return d
 
 
-@pytest.mark.parametrize("name", ["c1_cpinn_poisson", "c2_xpinn_poisson", "c3_cpinn_burgers", "c4_xpinn_kovasznay"])
+def _item_cost(nets, q, kind, count):
+    def c(n):
+        return count * (1 + (nets[n]["depth"] - 1) * nets[n]["wclass"] ** 2 * 24 + 40 * nets[n]["wclass"])
+    pair = nets[q]["pair"]
+    return c(q) + (c(pair) * 4 / 3 if pair >= 0 and kind in (0, 2) else 0)
+
+
+@pytest.mark.parametrize("name", ["c1_cpinn_poisson", "c2_xpinn_poisson", "c3_cpinn_burgers", "c4_xpinn_kovasznay",
+                                  "c5_xpinn_inverse_diffusion"])
 def test_plan_covers_every_point_once(name, tmp_path):
-    prob = W.make_problem(name, seed=0, scale=0.3)
+    prob = W.make_problem(name, seed=0, scale=0.05 if name.startswith("c5") else 0.3)
     d = _plan(prob, tmp_path, chunk_points=100)
+    nets = d["nets"]
     items = np.array(d["train_items"])
-    q, kind, begin, count, iface, side = (items[:, i] for i in range(6))
+    q, kind, begin, count, iface, side, lrow, prow = (items[:, i] for i in range(8))
     assert (count > 0).all() and (count <= 128).all()   # chunk rounded up to the 64-point tile
-    # residual and data points: each packed index in exactly one item
-    for k, total in ((0, d["n_res"]), (1, d["n_dat"])):
+    # residual, data and K-data points: each packed index in exactly one item
+    for k, total in ((0, d["n_res"]), (1, d["n_dat"]), (3, d["n_aux"])):
         cover = np.zeros(total, int)
         for b, c in zip(begin[kind == k], count[kind == k]):
             cover[b:b + c] += 1
@@ -53,30 +62,52 @@ def test_plan_covers_every_point_once(name, tmp_path):
     for b, c, s in zip(begin[kind == 2], count[kind == 2], side[kind == 2]):
         cover[b:b + c, s] += 1
     assert (cover == 1).all()
-    # items of an interface side belong to that side's subdomain
+    # items of an interface side belong to that side's subdomain; K data to a K-network
     for row in items[kind == 2]:
         e = d["ifaces"][row[4]]
-        assert row[0] == (e["a"] if row[5] == 0 else e["b"])
+        assert nets[row[0]]["sd"] == (e["a"] if row[5] == 0 else e["b"])
+    for row in items[kind == 3]:
+        assert nets[row[0]]["pair"] == -1 and nets[row[0] - 1]["pair"] == row[0]
     # descending cost order (fused path)
-    nets = d["nets"]
-    cost = [c * (1 + (nets[qq]["depth"] - 1) * nets[qq]["wclass"] ** 2 * 24 + 40 * nets[qq]["wclass"])
-            for qq, c in zip(q, count)]
+    cost = [_item_cost(nets, a, b, c) for a, b, c in zip(q, kind, count)]
     assert all(cost[i] >= cost[i + 1] for i in range(len(cost) - 1))
-    # partial rows are disjoint and sized to the subdomain's parameters
-    prow = items[:, 7]
+    # partial rows are disjoint, sized to the networks the item trains
+    paired = np.array([nets[a]["pair"] >= 0 and b in (0, 2) for a, b in zip(q, kind)])
+    size = np.array([nets[a]["gsize"] + (nets[nets[a]["pair"]]["gsize"] if pr else 0)
+                     for a, pr in zip(q, paired)])
     order = np.argsort(prow)
-    ends = prow[order] + np.array([nets[qq]["gsize"] for qq in q[order]])
+    ends = prow[order] + size[order]
     assert (ends[:-1] <= prow[order][1:]).all() and ends[-1] == d["partial_floats"]
-    # every item appears once in the per-subdomain row lists
-    rows = np.array(d["sd_rows"])
-    assert sorted(rows.tolist()) == list(range(len(items)))
-    ptr = d["sd_row_ptr"]
-    for qq in range(len(nets)):
-        assert (q[rows[ptr[qq]:ptr[qq + 1]]] == qq).all()
-    # parameter offsets follow the canonical layout sizes
-    for qq, s in enumerate(prob.subdomains):
-        assert nets[qq]["n_params"] == W.param_count(s.widths)
-        assert nets[qq]["wclass"] % 16 == 0 and nets[qq]["wclass"] >= s.widths[1]
+    # gradient rows: every item once under each network it trains, at that
+    # network's part of the item's row
+    ptr, ritem, rprow = d["net_row_ptr"], np.array(d["net_row_item"]), np.array(d["net_row_prow"])
+    seen = []
+    for n in range(len(nets)):
+        for r in range(ptr[n], ptr[n + 1]):
+            i = ritem[r]
+            if q[i] == n:
+                assert rprow[r] == prow[i]
+            else:
+                assert paired[i] and nets[q[i]]["pair"] == n and rprow[r] == prow[i] + nets[q[i]]["gsize"]
+            seen.append((n, i))
+    assert len(seen) == len(set(seen)) == len(items) + paired.sum()
+    # loss rows: every item once under its subdomain
+    lptr, lrows = d["sd_loss_ptr"], d["loss_rows"]
+    assert sorted(lrows) == sorted(lrow.tolist())
+    for sd in range(prob.n_sd):
+        for r in lrows[lptr[sd]:lptr[sd + 1]]:
+            assert nets[q[list(lrow).index(r)]]["sd"] == sd
+    # parameter offsets follow the canonical layout sizes: [u | K] per subdomain
+    sd_net = d["sd_net"]
+    for sd, s in enumerate(prob.subdomains):
+        u = nets[sd_net[sd]]
+        assert u["n_params"] == W.param_count(s.widths) and u["sd"] == sd
+        assert u["wclass"] % 16 == 0 and u["wclass"] >= s.widths[1]
+        if s.aux_widths is not None:
+            k = nets[sd_net[sd] + 1]
+            assert u["pair"] == sd_net[sd] + 1 and k["n_params"] == W.param_count(s.aux_widths)
+            assert k["poff"] == u["poff"] + u["n_params"]
+        assert sd_net[sd + 1] - sd_net[sd] == (2 if s.aux_widths is not None else 1)
 
 
 def _raw():
@@ -131,4 +162,26 @@ def test_create_rejects_bad_combinations():
     neg = (ct.c_double * 1)(-1.0)
     assert L.ddp_create(ct.byref(h), 1, 2, neg, 1) == ddpinn.DDP_EINVAL
     assert L.ddp_create(ct.byref(h), 1, 2, c, 1) == 0
+    assert L.ddp_destroy(h) == 0
+    # inverse diffusion: XPINN only, two networks per subdomain, K data only there
+    assert L.ddp_create(ct.byref(h), 0, 3, c, 0) == ddpinn.DDP_EINVAL
+    assert L.ddp_create(ct.byref(h), 1, 3, c, 0) == 0
+    lw = (ct.c_float * 4)(1, 1, 1, 1)
+    one = (ct.c_int * 1)(4)
+    w1 = (ct.c_int * 4)(2, 8, 8, 1)
+    assert L.ddp_add_subdomain(h, 1, one, w1, lw, 1e-3, None) == ddpinn.DDP_EINVAL
+    two = (ct.c_int * 2)(4, 3)
+    w2 = (ct.c_int * 7)(2, 8, 8, 1, 2, 6, 2)     # K-network with two outputs
+    assert L.ddp_add_subdomain(h, 2, two, w2, lw, 1e-3, None) == ddpinn.DDP_EINVAL
+    w2 = (ct.c_int * 7)(2, 8, 8, 1, 2, 6, 1)
+    assert L.ddp_add_subdomain(h, 2, two, w2, lw, 1e-3, None) == 0
+    n = ct.c_int64()
+    assert L.ddp_param_count(h, 0, ct.byref(n)) == 0 and n.value == W.param_count([2, 8, 8, 1]) + W.param_count([2, 6, 1])
+    xy = np.array([[0.1, 0.2]], np.float32)
+    v = np.ones(1, np.float32)
+    assert L.ddp_set_points(h, 0, 2, 1, xy.ctypes.data_as(ct.c_void_p), v.ctypes.data_as(ct.c_void_p), 0) == 0
+    assert L.ddp_destroy(h) == 0
+    assert L.ddp_create(ct.byref(h), 1, 0, c, 0) == 0
+    assert L.ddp_add_subdomain(h, 1, one, w1, lw, 1e-3, None) == 0
+    assert L.ddp_set_points(h, 0, 2, 1, xy.ctypes.data_as(ct.c_void_p), v.ctypes.data_as(ct.c_void_p), 0) == ddpinn.DDP_EINVAL
     assert L.ddp_destroy(h) == 0

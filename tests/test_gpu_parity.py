@@ -284,3 +284,70 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     pb.sync()
     pb.close()
     pb2.close()
+
+
+# --------------------------------------------------------------------------
+# inverse diffusion (Eq. heq): u- and K-network per subdomain, paired items
+
+
+@pytest.mark.parametrize("seed", [None, 51])
+def test_c5_inverse_scaled(seed):
+    prob = W.c5_xpinn_inverse_diffusion(seed=0, scale=0.03)
+    params = _params(prob, seed)
+    _say(f"c5 scale 0.03, perturbation {seed}")
+    pb, lt, g = run(prob, params)
+    wl, wg = compare(prob, params, lt, g)
+    _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+    pb.close()
+
+
+def test_c5_inverse_full_size_bench_launch():
+    prob = W.c5_xpinn_inverse_diffusion(seed=0)
+    params = _params(prob, None)
+    _say("c5 full size")
+    pb, lt, g = run(prob, params)
+    wl, wg = compare(prob, params, lt, g)
+    _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+    pb.close()
+
+
+def test_c5_inverse_narrow_ragged_fused_and_plain():
+    """Narrow and mixed widths for both networks (non-multiples of 16), short
+    point sets that end inside a tile, fused and per-subdomain launches."""
+    prob = W.c5_xpinn_inverse_diffusion(seed=3, scale=0.01)
+    rng = np.random.default_rng(0)
+    choices = [[2, 20, 1], [2, 33, 33, 1], [2, 40, 40, 40, 1], [2, 17, 17, 17, 17, 1]]
+    for q, s in enumerate(prob.subdomains):
+        s.widths = list(choices[q % 4])
+        s.aux_widths = list(choices[(q + 1) % 4])
+        s.params = np.concatenate([W.glorot_params(rng, s.widths), W.glorot_params(rng, s.aux_widths)])
+    params = _params(prob, 7)
+    for fused in (True, False):
+        _say(f"c5 narrow ragged fused={fused}")
+        pb, lt, g = run(prob, params, fused=fused, chunk_points=64)
+        compare(prob, params, lt, g)
+        pb.close()
+
+
+def test_c5_stitched_eval_and_adam_step():
+    prob = W.c5_xpinn_inverse_diffusion(seed=0, scale=0.02)
+    params = _params(prob, 61)
+    _say("c5 eval and one Adam step")
+    pb = ddpinn.Problem(prob, fused=True)
+    pb.set_params(params)
+    idx = np.arange(0, prob.eval_xy.shape[0], 23)
+    uk = pb.eval(prob.eval_xy[idx], prob.eval_owner[idx]).cpu().numpy()
+    ref = oracle.eval_stitched(prob, params, prob.eval_xy[idx], prob.eval_owner[idx])
+    assert uk.shape == ref.shape == (idx.size, 2)
+    np.testing.assert_allclose(uk, ref, rtol=1e-5, atol=1e-6)
+    _, grads = oracle.loss_and_grad(prob, params)
+    pb.step(1)
+    got = pb.get_params()
+    for q, s in enumerate(prob.subdomains):
+        th, _, _ = oracle.adam_step(params[q].astype(np.float64), 0.0, 0.0, grads[q], 1, s.lr)
+        # step 1 moves every parameter by about lr * sign(g): compare the step
+        step = got[q].astype(np.float64) - params[q].astype(np.float64)
+        ref_step = th - params[q].astype(np.float64)
+        big = np.abs(grads[q]) > 1e-3 * np.abs(grads[q]).max()
+        np.testing.assert_allclose(step[big], ref_step[big], rtol=2e-3, atol=2e-6 * s.lr)
+    pb.close()
