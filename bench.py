@@ -41,6 +41,13 @@ def algorithmic_flops(prob):
         depth = len(s.widths) - 2
         cols = 4 * s.res_xy.shape[0] + 1 * s.bnd_xy.shape[0] + s_if * n_if[q]
         total += 6.0 * cols * (depth - 1) * w * w
+        if s.aux_widths is not None:
+            # conductivity network of the inverse problem: value and gradient
+            # streams where the residual or the interface needs them, value at
+            # its data points
+            wk, dk = s.aux_widths[1], len(s.aux_widths) - 2
+            colk = 3 * s.res_xy.shape[0] + 1 * s.aux_xy.shape[0] + 3 * n_if[q]
+            total += 6.0 * colk * (dk - 1) * wk * wk
     return total
 
 
@@ -102,6 +109,8 @@ def main():
                     help="profiling mode: set up the fused step, then launch only the train kernel N times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="profiling mode: copy a float32 buffer of MIB MiB 5 times (byte-counter calibration)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="report another workload (the benchmark line is the 16-subdomain XPINN Poisson one)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
@@ -121,7 +130,7 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}))
         return
 
-    prob = W.make_problem(WORKLOAD, seed=args.seed)
+    prob = W.make_problem(args.workload, seed=args.seed)
     if args.kernel_only:
         pb = ddpinn.Problem(prob, fused=True, device="cuda:0", chunk_points=args.chunk_points)
         pb.step(2)
@@ -163,14 +172,16 @@ def main():
 
     achieved = flops / (kt["train_ms"] * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": traffic_from_profile(1),
+            "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+            "traffic": traffic_from_profile(1) if args.workload == WORKLOAD else None,
             "kernel": "k_train", "kernel_ms": kt["train_ms"], "algorithmic_flop_per_launch": flops}
     out = {
         "metric": METRIC, "value": n_res / (ms_fused * 1e-3), "unit": "residual points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_fused, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "xpinn_poisson2d_4x4_uneven (16 subdomains, widths {20,40,60,80}, 3-6 hidden "
-                               "layers, U[2k,20k] residual pts, 200 pts/interface)",
+        "config": {"workload": ("xpinn_poisson2d_4x4_uneven (16 subdomains, widths {20,40,60,80}, 3-6 hidden "
+                                "layers, U[2k,20k] residual pts, 200 pts/interface)")
+                   if args.workload == WORKLOAD else args.workload,
                    "seed": args.seed, "n_residual": n_res, "parallelism": "single GPU, fused persistent launch"},
         "steps_per_s": 1e3 / ms_fused,
         "plain": plain,
