@@ -310,6 +310,18 @@ struct Tile {
     for (int idx = tid; idx < N4; idx += NT) d4[idx] = s4[idx];
   }
 
+  // A forward layer's weights and bias go to LDS as [WP][WS] then [WP]: the
+  // hidden layer then reads its bias from LDS between its stash stores, and a
+  // global load there would have to wait for those stores to drain (one
+  // in-order counter covers vector loads and stores).
+  static constexpr int NWB4 = (WP * WS + WP) / 4;            // float4 of weights + bias
+  __device__ static void stage_wb(float* sW, const float* srcW, const float* srcB, int tid) {
+    constexpr int N4 = WP * WS / 4;
+    f4* d4 = reinterpret_cast<f4*>(sW);
+    for (int idx = tid; idx < NWB4; idx += NT)
+      d4[idx] = idx < N4 ? reinterpret_cast<const f4*>(srcW)[idx] : reinterpret_cast<const f4*>(srcB)[idx - N4];
+  }
+
   // One hidden layer, output block by output block: a^k_mb = W^k h^{k-1}
   // (+ b^k on the value stream) for all four streams, stash a^k_mb, and the
   // tanh rule into the new activations Hn (H stays intact as the B operand).
@@ -585,10 +597,10 @@ struct Tile {
     const __amdgpu_buffer_rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(lds, 0, 0, 0x00020000);  // unused
     for (int k = 2; k <= nd.depth; ++k) {
       __syncthreads();
-      stage(sW, K + L.k_w(k), tid);
+      stage_wb(sW, K + L.k_w(k), K + L.k_b(k), tid);
       __syncthreads();
       Streams Hn;
-      hidden_layer<false>(sW, K + L.k_b(k), g, pc, H, Hn, none, 0, wave, lane);
+      hidden_layer<false>(sW, sW + WP * WS, g, pc, H, Hn, none, 0, wave, lane);
 #pragma unroll
       for (int st = 0; st < 4; ++st)
 #pragma unroll
@@ -627,7 +639,7 @@ struct Tile {
                                    float* slot, const float* sNb, float* sInv, int t_lo, int t_hi,
                                    int roff) {
     float* sW = lds;
-    float* sA = sW + WP * WS;
+    float* sA = sW + WP * WS + WP;   // after the staged weights and bias
     float* sH = sA + WP * TPS;
     float* sU = sH + WP * TPS;       // [4 streams][3 outputs][TP]
     float* sX = sU + 4 * 3 * TP;     // [2][TP]
@@ -677,10 +689,10 @@ struct Tile {
         tp = wave * 16 + pc;
         stash_store(rs, 1, k - 2, wave, lane, H);   // h^{k-1}
         __syncthreads();
-        stage(sW, K + L.k_w(k), tid);
+        stage_wb(sW, K + L.k_w(k), K + L.k_b(k), tid);
         __syncthreads();
         Streams Hn;
-        hidden_layer<true>(sW, K + L.k_b(k), g, pc, H, Hn, rs, k - 2, wave, lane);   // stashes a^k
+        hidden_layer<true>(sW, sW + WP * WS, g, pc, H, Hn, rs, k - 2, wave, lane);   // stashes a^k
 #pragma unroll
         for (int st = 0; st < 4; ++st)
 #pragma unroll
@@ -935,7 +947,7 @@ struct Tile {
 // seeds, the neighbour's K streams.
 template <int WP, int PDE>
 constexpr int lds_tile_floats() {
-  return WP * (WP + 4) + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms;
+  return WP * (WP + 4) + WP + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms;
 }
 template <int WP, int PDE>
 constexpr int lds_train_floats() {
