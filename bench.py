@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--chunk-points", type=int, default=None)
+    ap.add_argument("--no-autotune", action="store_true", help="time the default work plan")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="N",
                     help="profiling mode: set up the fused step, then launch only the train kernel N times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -133,6 +134,8 @@ def main():
     prob = W.make_problem(args.workload, seed=args.seed)
     if args.kernel_only:
         pb = ddpinn.Problem(prob, fused=True, device="cuda:0", chunk_points=args.chunk_points)
+        if not args.no_autotune:
+            pb.autotune(iters=10)
         pb.step(2)
         kt = pb.time_kernels(args.kernel_only)
         pb.close()
@@ -146,6 +149,12 @@ def main():
 
     def time_path(fused):
         pb = ddpinn.Problem(prob, fused=fused, device=dev, stream=stream, chunk_points=args.chunk_points)
+        plan = None
+        if not args.no_autotune:
+            # work-plan choice (points per item, items per workgroup, workgroups
+            # per CU) by the library's autotuner; set-up, outside the timed steps
+            plan = pb.autotune(iters=10)
+        pb.plan = plan
         pb.step(args.warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -158,6 +167,7 @@ def main():
         return pb, ms
 
     pf, ms_fused = time_path(True)
+    plan_fused = pf.plan
     print(f"# fused: {ms_fused:.4f} ms/step", file=sys.stderr, flush=True)
     kt = pf.time_kernels(max(10, min(args.steps, 50)))
     print(f"# kernels: {kt}", file=sys.stderr, flush=True)
@@ -167,7 +177,7 @@ def main():
         pp, ms_plain = time_path(False)
         pp.close()
         plain = {"value": n_res / (ms_plain * 1e-3), "ms_per_step": ms_plain,
-                 "steps_per_s": 1e3 / ms_plain}
+                 "steps_per_s": 1e3 / ms_plain, "plan": pp.plan}
         print(f"# plain: {ms_plain:.4f} ms/step", file=sys.stderr, flush=True)
 
     achieved = flops / (kt["train_ms"] * 1e-3) / 1e12
@@ -182,7 +192,8 @@ def main():
         "config": {"workload": ("xpinn_poisson2d_4x4_uneven (16 subdomains, widths {20,40,60,80}, 3-6 hidden "
                                 "layers, U[2k,20k] residual pts, 200 pts/interface)")
                    if args.workload == WORKLOAD else args.workload,
-                   "seed": args.seed, "n_residual": n_res, "parallelism": "single GPU, fused persistent launch"},
+                   "seed": args.seed, "n_residual": n_res, "parallelism": "single GPU, fused persistent launch",
+                   "plan": plan_fused},
         "steps_per_s": 1e3 / ms_fused,
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_fused) if plain else None,

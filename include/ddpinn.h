@@ -118,7 +118,8 @@ int ddp_set_option(ddp_problem* p, int option, int64_t value);
 int ddp_finalize(ddp_problem* p, void* hip_stream, int fused);
 
 /* Autotuner: time candidate work plans on this problem (points per item
- * bound, items per resident workgroup, workgroups per compute unit) with
+ * bound 256..2048, items per resident workgroup 1..8, workgroups per compute
+ * unit 1..as many as fit) with
  * iters loss-and-gradient passes each, keep the fastest and rebuild the step
  * graph with it.  Parameters and Adam state are not changed.  cache_path (may
  * be NULL) is a JSON-lines file of earlier choices keyed by a signature of the

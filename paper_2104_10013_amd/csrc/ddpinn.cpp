@@ -838,8 +838,8 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
     hipEvent_t ev[2];
     HIP_TRY(hipEventCreate(&ev[0]));
     HIP_TRY(hipEventCreate(&ev[1]));
-    const int64_t chunks[] = {512, 1024, 2048};
-    const int ipss[] = {2, 4, 8};
+    const int64_t chunks[] = {256, 512, 1024, 2048};
+    const int ipss[] = {1, 2, 4, 8};
     for (int64_t c : chunks) {
       for (int ips : ipss) {
         for (int bpc = 1; bpc <= p->occupancy; ++bpc) {

@@ -23,10 +23,11 @@ def layer_slices(widths, aux_widths=None):
     return out
 
 
-def compare(prob, params, lt_gpu, g_gpu, loss_rtol=LOSS_RTOL, grad_rtol=GRAD_RTOL, per_layer=True):
-    """Compare GPU loss terms / gradients with the FP64 oracle; returns the
-    worst relative errors (loss, grad) and raises AssertionError on failure."""
-    terms, grads = oracle.loss_and_grad(prob, params)
+def compare(prob, params, lt_gpu, g_gpu, loss_rtol=LOSS_RTOL, grad_rtol=GRAD_RTOL, per_layer=True, ref=None):
+    """Compare GPU loss terms / gradients with the FP64 oracle (or with ref =
+    (terms, grads) it computed before); returns the worst relative errors
+    (loss, grad) and raises AssertionError on failure."""
+    terms, grads = ref if ref is not None else oracle.loss_and_grad(prob, params)
     lt = np.asarray(lt_gpu, np.float64)
     worst_l, worst_g = 0.0, 0.0
     for q in range(prob.n_sd):

@@ -58,14 +58,22 @@ def test_c2_xpinn_poisson_scaled(seed):
 
 def test_c2_xpinn_poisson_full_size_bench_launch():
     """Full-size 16-subdomain workload in the launch configuration the
-    benchmark times (fused, default chunking)."""
+    benchmark times (fused, work plan chosen by the autotuner), and with the
+    default plan."""
     prob = W.c2_xpinn_poisson(seed=0)
     params = _params(prob, None)
-    _say("c2 full size")
-    pb, lt, g = run(prob, params)
-    wl, wg = compare(prob, params, lt, g)
-    _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
-    pb.close()
+    terms, grads = oracle.loss_and_grad(prob, params)
+    for tuned in (True, False):
+        _say(f"c2 full size, autotuned plan {tuned}")
+        pb = ddpinn.Problem(prob, fused=True)
+        if tuned:
+            _say(f"  plan {pb.autotune(iters=3)}")
+        lt, g = pb.loss_and_grad()
+        torch.cuda.synchronize()
+        wl, wg = compare(prob, params, lt.cpu().numpy(), [x.cpu().numpy() for x in pb.split(g.cpu())],
+                         ref=(terms, grads))
+        _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+        pb.close()
 
 
 def test_ragged_mixed_widths_and_depths():
