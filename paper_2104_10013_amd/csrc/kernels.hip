@@ -325,8 +325,13 @@ struct Tile {
   // One hidden layer, output block by output block: a^k_mb = W^k h^{k-1}
   // (+ b^k on the value stream) for all four streams, stash a^k_mb, and the
   // tanh rule into the new activations Hn (H stays intact as the B operand).
+  // rq: MFMA steps of the last 16-neuron input block that hold real neurons
+  // (neuron_pos puts neurons 4i..4i+3 of a block in step i); the rest of that
+  // block is zero padding and is skipped.
+  __device__ static int real_steps(int width) { return (width - (WP - 16) + 3) >> 2; }
+
   template <bool STASH>
-  __device__ static void hidden_layer(const float* sW, const float* bias, int g, int pc, const Streams& H,
+  __device__ static void hidden_layer(const float* sW, const float* bias, int g, int pc, int rq, const Streams& H,
                                       Streams& Hn, __amdgpu_buffer_rsrc_t rs, int layer, int wave, int lane) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
@@ -340,6 +345,7 @@ struct Tile {
         const f4 wv = *reinterpret_cast<const f4*>(&sW[(16 * mb + pc) * WS + 16 * kb + 4 * g]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
+          if (kb == MB - 1 && i >= rq) continue;
 #pragma unroll
           for (int s = 0; s < 4; ++s) acc[s] = mma(wv[i], H[s][kb][i], acc[s]);
         }
@@ -362,7 +368,9 @@ struct Tile {
   }
 
   // g^{k-1}_s = W^{kT} abar^k_s for one stream (sW holds W^T)
-  __device__ static void hidden_bwd_stream(const float* sWT, int g, int pc, const f4 (&Ab)[MB], f4 (&Gs)[MB]) {
+  // (rq as in hidden_layer: padded output neurons of layer k contribute nothing)
+  __device__ static void hidden_bwd_stream(const float* sWT, int g, int pc, int rq, const f4 (&Ab)[MB],
+                                           f4 (&Gs)[MB]) {
 #pragma unroll
     for (int jb = 0; jb < MB; ++jb) Gs[jb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -372,7 +380,10 @@ struct Tile {
       for (int jb = 0; jb < MB; ++jb) {
         const f4 wv = *reinterpret_cast<const f4*>(&sWT[(16 * jb + pc) * WS + 16 * mb + 4 * g]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) Gs[jb] = mma(wv[i], Ab[mb][i], Gs[jb]);
+        for (int i = 0; i < 4; ++i) {
+          if (mb == MB - 1 && i >= rq) continue;
+          Gs[jb] = mma(wv[i], Ab[mb][i], Gs[jb]);
+        }
       }
     }
   }
@@ -463,7 +474,7 @@ struct Tile {
   // L = K Lap u + K_x u_x + K_y u_y (Eq. heq expanded), and kb receives the
   // seeds of (K, K_x, K_y).  EPI_SEED: the seeds come from inv + 3 TP.
   template <int MODE>
-  __device__ static void epilogue(const KArgs& ka, const Item& it, const NetDesc& nd, int pt, int tp, bool valid,
+  __device__ __forceinline__ static void epilogue(const KArgs& ka, const Item& it, const NetDesc& nd, int pt, int tp, bool valid,
                                   const float* nb, const float* inv, const float (&u)[DO][4], float (&ub)[DO][4],
                                   float (&loss)[kLossTerms], float (&kb)[3]) {
 #pragma unroll
@@ -574,7 +585,7 @@ struct Tile {
   //  VAL_INV_NB   (u, K, L(u, K)) of a neighbour's u-network, with its K streams
   //               read from kin.
   template <int VMODE>
-  __device__ static void values_tile(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* dst,
+  __device__ __forceinline__ static void values_tile(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* dst,
                                      const float* kin, int t0) {
     float* sW = lds;
     const int tid = item_tid();
@@ -600,7 +611,7 @@ struct Tile {
       stage_wb(sW, K + L.k_w(k), K + L.k_b(k), tid);
       __syncthreads();
       Streams Hn;
-      hidden_layer<false>(sW, sW + WP * WS, g, pc, H, Hn, none, 0, wave, lane);
+      hidden_layer<false>(sW, sW + WP * WS, g, pc, real_steps(nd.width), H, Hn, none, 0, wave, lane);
 #pragma unroll
       for (int st = 0; st < 4; ++st)
 #pragma unroll
@@ -635,7 +646,7 @@ struct Tile {
   // offset of this network's part in the item's gradient row; MODE selects the
   // epilogue (sInv: the LDS exchange area of the inverse problem).
   template <bool PREFETCH_A, int MODE>
-  __device__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
+  __device__ __forceinline__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                    float* slot, const float* sNb, float* sInv, int t_lo, int t_hi,
                                    int roff) {
     float* sW = lds;
@@ -692,7 +703,8 @@ struct Tile {
         stage_wb(sW, K + L.k_w(k), K + L.k_b(k), tid);
         __syncthreads();
         Streams Hn;
-        hidden_layer<true>(sW, sW + WP * WS, g, pc, H, Hn, rs, k - 2, wave, lane);   // stashes a^k
+        hidden_layer<true>(sW, sW + WP * WS, g, pc, real_steps(nd.width), H, Hn, rs, k - 2, wave,
+                           lane);   // stashes a^k
 #pragma unroll
         for (int st = 0; st < 4; ++st)
 #pragma unroll
@@ -842,7 +854,7 @@ struct Tile {
           __syncthreads();
           {
             f4 Gs[MB];
-            hidden_bwd_stream(sW, g, pc, Ab[s], Gs);
+            hidden_bwd_stream(sW, g, pc, real_steps(nd.width), Ab[s], Gs);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
@@ -935,7 +947,7 @@ struct Tile {
   // registers, so it is used for classes up to 48 in kernels that run two
   // waves per SIMD anyway because of a wider class
   template <int WPMAX, int MODE>
-  __device__ static void train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* slot,
+  __device__ __forceinline__ static void train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* slot,
                                const float* sNb, float* sInv, int t_lo, int t_hi, int roff) {
     run_train<(WP <= 48 && WPMAX >= 48), MODE>(ka, it, nd, lds, slot, sNb, sInv, t_lo, t_hi, roff);
   }
@@ -1057,6 +1069,14 @@ __global__ __launch_bounds__(NT, min_waves_per_eu<WPMAX>()) void k_train(KArgs k
   }
 }
 
+// Position of hidden neuron n in the kernel layout and the gradient rows: the
+// index inside each 16-neuron block is transposed as a 4x4 grid (4a + b ->
+// 4b + a).  Register i of lane group g then holds neuron 16 mb + 4 i + g, so
+// the MFMA step i of a contraction over a block covers four consecutive
+// neurons, and in a padded last block the steps past the real neurons can be
+// skipped.  The map is its own inverse.
+__host__ __device__ __forceinline__ int neuron_pos(int n) { return (n & ~15) | ((n & 3) << 2) | ((n >> 2) & 3); }
+
 // Position of canonical parameter li of a network in its gradient partial row
 // (g) and in its kernel-layout copy (k1, and k2 for the transposed copy of a
 // hidden weight, else -1).
@@ -1066,11 +1086,11 @@ __device__ __forceinline__ void param_map(const NetDesc& nd, int li, int& g, int
   k2 = -1;
   if (li < 2 * w) {                 // W^1[m][c]
     const int m = li >> 1, c = li & 1;
-    g = k1 = m * 4 + c;
+    g = k1 = neuron_pos(m) * 4 + c;
     return;
   }
   if (li < 3 * w) {                 // b^1[m]
-    g = k1 = (li - 2 * w) * 4 + 2;
+    g = k1 = neuron_pos(li - 2 * w) * 4 + 2;
     return;
   }
   int r = li - 3 * w;
@@ -1080,12 +1100,12 @@ __device__ __forceinline__ void param_map(const NetDesc& nd, int li, int& g, int
     const int k = h + 2;
     const int rr = r - h * per;
     if (rr < w * w) {
-      const int m = rr / w, j = rr - (rr / w) * w;
+      const int m = neuron_pos(rr / w), j = neuron_pos(rr - (rr / w) * w);
       g = L.g_w(k) + m * WP + j;
       k1 = L.k_w(k) + m * L.WS + j;
       k2 = L.k_wt(k) + j * L.WS + m;
     } else {
-      const int m = rr - w * w;
+      const int m = neuron_pos(rr - w * w);
       g = L.g_b(k) + m;
       k1 = L.k_b(k) + m;
     }
@@ -1093,7 +1113,7 @@ __device__ __forceinline__ void param_map(const NetDesc& nd, int li, int& g, int
   }
   r -= (D - 1) * per;               // output layer
   if (r < DO * w) {
-    const int c = r / w, j = r - (r / w) * w;
+    const int c = r / w, j = neuron_pos(r - (r / w) * w);
     g = L.g_out() + c * WP + j;
     k1 = L.k_out() + c * WP + j;
   } else {
