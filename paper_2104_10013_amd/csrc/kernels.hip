@@ -845,16 +845,20 @@ struct Tile {
         Streams& Ab = G;
         __syncthreads();
         stage(sW, K + L.k_wt(k), tid);
+        __syncthreads();
         // per stream: g^{k-1}_s = W^{kT} abar^k_s, then the stream's share of
-        // dW^k = sum_{points, streams} abar^k h^{k-1 T}; db^k = sum_points abar^k_0
+        // dW^k = sum_{points, streams} abar^k h^{k-1 T}; db^k = sum_points abar^k_0.
+        // The barrier that frees sA/sH from the previous stream's dW comes after
+        // the W^T abar products, which only read sW: a wave that finished its
+        // dW blocks early goes on with them.
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           f4 Hs[MB];
           stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s (stored in the forward)
-          __syncthreads();
           {
             f4 Gs[MB];
             hidden_bwd_stream(sW, g, pc, real_steps(nd.width), Ab[s], Gs);
+            if (s > 0) __syncthreads();
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
