@@ -269,6 +269,8 @@ struct Tile {
   static constexpr int NB = (NBT + kWaves - 1) / kWaves;    // dW blocks per wave
   static constexpr int KL = (DO * WP + NT - 1) / NT;        // output-layer slots per thread
   static constexpr int STASH_LAYER = kWaves * 4 * MB * 1024;  // bytes of one layer's stash
+  // the staged-weight buffer (WP x WS + WP floats) can take a WP x TPS tile
+  static constexpr bool kL1InW = WP * WS + WP >= WP * TPS;
 
   typedef f4 Streams[4][MB];
 
@@ -768,20 +770,23 @@ struct Tile {
         accL[r] = t < DO * WP ? prior(R + L.g_out() + t, first) : 0.f;
       }
       float accB = tid < DO ? prior(R + L.g_bout() + tid, first) : 0.f;
+      // h^D streams staged alternately in sH and sA (both free here): a buffer
+      // is rewritten two streams later, after every wave has passed the
+      // barrier of the stream in between, so one barrier per stream suffices
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        __syncthreads();
+        float* sB = (s & 1) ? sA : sH;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sH[(16 * mb + 4 * g + i) * TPS + tp] = H[s][mb][i];
+          for (int i = 0; i < 4; ++i) sB[(16 * mb + 4 * g + i) * TPS + tp] = H[s][mb][i];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < KL; ++r) {
           const int t = tid + r * NT;
           if (t < DO * WP) {
             const int c = t / WP, j = t - (t / WP) * WP;
-            accL[r] = row_dot(sU + (s * 3 + c) * TP, sH + j * TPS, accL[r]);
+            accL[r] = row_dot(sU + (s * 3 + c) * TP, sB + j * TPS, accL[r]);
           }
         }
         if (s == 0 && tid < DO) accB += row_sum(sU + tid * TP);
@@ -919,9 +924,12 @@ struct Tile {
             float a0, a1, a2, a3;
             tanh_adj<S2>(A1[0][mb][i], A1[1][mb][i], A1[2][mb][i], A1[3][mb][i], G[0][mb][i], G[1][mb][i],
                          G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
+            // abar^1 streams: value to sA, d/dz0 to sH, d/dz1 to sW where the
+            // staged-weight buffer (free in this block) holds WP x TPS floats
             sA[(16 * mb + 4 * g + i) * TPS + tp] = a0;
             sH[(16 * mb + 4 * g + i) * TPS + tp] = a1;
-            G[2][mb][i] = a2;
+            if constexpr (kL1InW) sW[(16 * mb + 4 * g + i) * TPS + tp] = a2;
+            else G[2][mb][i] = a2;
           }
         }
         __syncthreads();
@@ -930,14 +938,16 @@ struct Tile {
           dw0 = row_dot_plus(sA + tid * TPS, sX, sH + tid * TPS);
           db = row_sum(sA + tid * TPS);
         }
-        __syncthreads();
+        if constexpr (!kL1InW) {
+          __syncthreads();
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+          for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sH[(16 * mb + 4 * g + i) * TPS + tp] = G[2][mb][i];
-        __syncthreads();
+            for (int i = 0; i < 4; ++i) sH[(16 * mb + 4 * g + i) * TPS + tp] = G[2][mb][i];
+          __syncthreads();
+        }
         if (tid < WP) {
-          dw1 = row_dot_plus(sA + tid * TPS, sX + TP, sH + tid * TPS);
+          dw1 = row_dot_plus(sA + tid * TPS, sX + TP, (kL1InW ? sW : sH) + tid * TPS);
           R[4 * tid] = p0 + dw0;
           R[4 * tid + 1] = p1 + dw1;
           R[4 * tid + 2] = p2 + db;
