@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--chunk-points", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true", help="time the default work plan")
+    ap.add_argument("--autotune-cache", default=None, metavar="PATH",
+                    help="JSON-lines cache of autotuner choices (a hit skips the search)")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="N",
                     help="profiling mode: set up the fused step, then launch only the train kernel N times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -135,7 +137,7 @@ def main():
     if args.kernel_only:
         pb = ddpinn.Problem(prob, fused=True, device="cuda:0", chunk_points=args.chunk_points)
         if not args.no_autotune:
-            pb.autotune(iters=10)
+            pb.autotune(iters=10, cache_path=args.autotune_cache)
         pb.step(2)
         kt = pb.time_kernels(args.kernel_only)
         pb.close()
@@ -153,7 +155,7 @@ def main():
         if not args.no_autotune:
             # work-plan choice (points per item, items per workgroup, workgroups
             # per CU) by the library's autotuner; set-up, outside the timed steps
-            plan = pb.autotune(iters=10)
+            plan = pb.autotune(iters=10, cache_path=args.autotune_cache)
         pb.plan = plan
         pb.step(args.warmup)
         torch.cuda.synchronize()

@@ -119,17 +119,17 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused);
 
 /* Autotuner: time candidate work plans on this problem (points per item
  * bound 256..2048, items per resident workgroup 1..8, workgroups per compute
- * unit 1..as many as fit) with
- * iters loss-and-gradient passes each, keep the fastest and rebuild the step
- * graph with it.  Parameters and Adam state are not changed.  cache_path (may
- * be NULL) is a JSON-lines file of earlier choices keyed by a signature of the
- * problem (operator, method, widths, depths, point counts, CU count): a hit
- * skips the search, a miss appends the new choice.  choice (may be NULL)
- * receives the 3 chosen values.  Not safe to call while the caller's stream
- * runs other work on this problem. */
+ * unit 1..as many as fit) with iters loss-and-gradient passes each, keep the
+ * fastest and rebuild the step graph with it.  Parameters and Adam state are
+ * not changed.  cache_path (may be NULL) is a JSON-lines file of earlier
+ * choices keyed by a signature of the problem (operator, method, fused or
+ * per-subdomain path, widths, depths, point counts, CU count): a hit skips
+ * the search, a miss appends the new choice.  choice (may be NULL) receives
+ * the 3 chosen values.  Not safe to call while the caller's stream runs other
+ * work on this problem. */
 int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* choice);
 
-/* Number of parameters of subdomain sd's network (canonical layout). */
+/* Number of parameters of subdomain sd (its networks' canonical layouts, concatenated). */
 int ddp_param_count(const ddp_problem* p, int sd, int64_t* n);
 
 /* Copy subdomain sd's parameters in (set) or out (get), canonical layout.

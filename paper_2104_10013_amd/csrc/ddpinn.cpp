@@ -747,6 +747,7 @@ uint64_t problem_signature(const ddp_problem* p) {
   };
   mix(p->pde);
   mix(p->method);
+  mix(p->fused);
   mix(p->n_cu);
   mix((int64_t)p->sds.size());
   for (const HostSd& s : p->sds) {
