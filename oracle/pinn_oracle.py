@@ -260,7 +260,10 @@ def loss_and_grad(prob, params, grad_mode="local"):
             terms.append(t.detach().numpy())
             grads.append(None)
             continue
-        g, = torch.autograd.grad(t[0], thetas[q], allow_unused=True)
+        if t[0].requires_grad:
+            g, = torch.autograd.grad(t[0], thetas[q], allow_unused=True)
+        else:
+            g = None   # no points at all: J_q is the constant 0 (empty means are 0)
         if g is None:
             g = torch.zeros_like(thetas[q])
         terms.append(t.detach().numpy())

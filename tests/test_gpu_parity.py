@@ -359,3 +359,32 @@ def test_c5_stitched_eval_and_adam_step():
         big = np.abs(grads[q]) > 1e-3 * np.abs(grads[q]).max()
         np.testing.assert_allclose(step[big], ref_step[big], rtol=2e-3, atol=2e-6 * s.lr)
     pb.close()
+
+
+def test_extreme_network_sizes_and_an_empty_subdomain():
+    """Maximum sizes (width 112 with 8 hidden layers, the widest class and
+    deepest stash), the narrowest networks (widths 1, 3 and 16), Navier-Stokes
+    outputs on a wide net, and a subdomain without any points (zero loss and
+    gradient, parameters unchanged by Adam)."""
+    widths = [[2] + [112] * 8 + [1], [2, 1, 1], [2, 3, 3, 3, 1], [2] + [16] * 7 + [1]]
+    prob = W.custom_box_problem("xpinn", "poisson2d", 2, 2, widths, [150, 70, 1, 0], n_bnd_seg=5, n_iface=19,
+                                seed=11)
+    # the fourth box keeps no points at all: no data, no interfaces
+    s3 = prob.subdomains[3]
+    s3.bnd_xy, s3.bnd_g = s3.bnd_xy[:0], s3.bnd_g[:0]
+    prob.interfaces = [e for e in prob.interfaces if 3 not in (e.a, e.b)]
+    params = _params(prob, 13)
+    _say("extreme sizes and an empty subdomain")
+    pb, lt, g = run(prob, params, chunk_points=64)
+    compare(prob, params, lt, g)
+    assert np.all(lt[3] == 0) and np.all(g[3] == 0)
+    pb.step(1)
+    assert np.array_equal(pb.get_params()[3], params[3])
+    pb.close()
+    prob = W.custom_box_problem("xpinn", "ns2d_steady", 2, 1, [[2] + [112] * 3 + [3], [2, 7, 7, 3]], [90, 40],
+                                n_bnd_seg=6, n_iface=23, seed=12, coef=(40.0,), domain=(-0.5, 1.0, -0.5, 1.5))
+    params = _params(prob, 14)
+    _say("navier-stokes width 112")
+    pb, lt, g = run(prob, params)
+    compare(prob, params, lt, g)
+    pb.close()

@@ -476,3 +476,14 @@ def test_inverse_local_gradient_vs_gradient_of_total():
     _, g_iface = O.loss_and_grad(prob_i, params)
     for q in range(prob.n_sd):
         np.testing.assert_allclose(g_total[q], g_local[q] + g_iface[q], rtol=1e-10, atol=1e-13)
+
+
+def test_subdomain_without_points_has_zero_loss_and_gradient():
+    """A subdomain with no residual, data or interface points: every mean is
+    over an empty set (0), so J_q = 0 and its gradient is 0."""
+    prob = W.custom_box_problem("xpinn", "poisson2d", 2, 1, [[2, 4, 4, 1], [2, 3, 1]], [9, 0], n_bnd_seg=0,
+                                n_iface=0, seed=1)
+    prob.interfaces = []
+    terms, grads = O.loss_and_grad(prob, [s.params for s in prob.subdomains])
+    assert np.all(terms[1] == 0) and np.all(grads[1] == 0) and grads[1].shape == prob.subdomains[1].params.shape
+    assert terms[0, 2] > 0 and np.linalg.norm(grads[0]) > 0
