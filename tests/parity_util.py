@@ -48,7 +48,7 @@ def compare(prob, params, lt_gpu, g_gpu, loss_rtol=LOSS_RTOL, grad_rtol=GRAD_RTO
             for k, sl in enumerate(layer_slices(sd.widths, sd.aux_widths)):
                 r = ref[sl]
                 nr = np.linalg.norm(r)
-                if nr < 1e-6 * nref:
+                if nr == 0.0 or nr < 1e-6 * nref:   # (a zero gradient is checked as a whole above)
                     continue
                 e = np.linalg.norm(g[sl] - r) / nr
                 assert e <= 10 * grad_rtol, f"sd {q} tensor {k} rel {e:.3e}"
