@@ -37,12 +37,13 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c1_cpinn_poisson", choices=sorted(W.WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--scale", type=float, default=1.0, help="point-count scale of the workload")
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--report-every", type=int, default=0, help="0: only at the end")
     ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args(argv)
 
-    prob = W.make_problem(args.workload, seed=args.seed)
+    prob = W.make_problem(args.workload, seed=args.seed, scale=args.scale)
     pb = ddpinn.Problem(prob, fused=True)
     if not args.no_autotune:
         pb.autotune(iters=5)
@@ -61,7 +62,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     final = stitched_errors(pb, prob)
-    print(json.dumps({"workload": args.workload, "seed": args.seed, "steps": args.steps,
+    print(json.dumps({"workload": args.workload, "seed": args.seed, "scale": args.scale, "steps": args.steps,
                       "rel_l2_init": init, "rel_l2_final": final, "train_s": secs,
                       "steps_per_s": args.steps / secs}), flush=True)
     pb.close()

@@ -388,3 +388,16 @@ def test_extreme_network_sizes_and_an_empty_subdomain():
     pb, lt, g = run(prob, params)
     compare(prob, params, lt, g)
     pb.close()
+
+
+def test_c5_training_trajectory_loosely_follows_oracle():
+    """30 Adam steps of a small inverse problem (both networks per cell): the
+    per-subdomain losses follow the FP64 oracle's trajectory."""
+    prob = W.c5_xpinn_inverse_diffusion(seed=1, scale=0.02)
+    n = 30
+    _say("c5 trajectory 30 steps")
+    pb = ddpinn.Problem(prob, fused=True)
+    hist = np.stack([pb.step(1).cpu().numpy().copy() for _ in range(n)])
+    _, hist_ref = oracle.train(prob, [s.params for s in prob.subdomains], n)
+    np.testing.assert_allclose(hist[:, :, 0], hist_ref[:, :, 0], rtol=2e-3)
+    pb.close()
