@@ -702,7 +702,7 @@ int install_plan(ddp_problem* p) {
   p->n_slots = std::max(1, p->n_cu * bpc);
   p->plan_slots = p->n_slots;
   if (int rc = build_plan(p)) return rc;
-  p->slot_floats = scratch_slot_floats(p->wpmax);
+  p->slot_floats = scratch_slot_floats(p->pde, p->wpmax);
   p->n_counters = n_sd + 1;
   int rc = 0;
   if ((rc = plan_upload(p, &p->d_counters, std::vector<int>(p->n_counters, 0)))) return rc;

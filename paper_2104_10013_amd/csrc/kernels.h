@@ -8,7 +8,7 @@ namespace ddp {
 // dynamic LDS bytes of the train kernel for a width class
 size_t lds_bytes(int pde, int wpmax);
 // floats of one workgroup's activation stash for the widest class wpmax
-int64_t scratch_slot_floats(int wpmax);
+int64_t scratch_slot_floats(int pde, int wpmax);
 // resident train workgroups per compute unit (also raises the LDS limit)
 hipError_t train_occupancy(int pde, int wpmax, int* blocks_per_cu);
 

@@ -231,6 +231,12 @@ enum {
   EPI_INV_U = 1,  // u-network of a paired inverse item: loss, u seeds, and the K seeds into LDS
   EPI_SEED = 2    // K-network of a paired inverse item: output seeds read from LDS, no loss
 };
+// parts of a train tile
+enum {
+  PH_ALL = 0,  // forward, loss / seeds, reverse pass
+  PH_FWD = 1,  // forward only (stashed), output streams (value, d/dz0, d/dz1) to LDS
+  PH_BWD = 2   // reverse pass only, from the stash of an earlier PH_FWD of the same tile
+};
 // values_tile modes
 enum {
   VAL_OWN = 0,     // interface values of the item's method (u, then flux.n or L(u))
@@ -646,11 +652,12 @@ struct Tile {
   // the output layer runs) instead of at the top of each reverse layer.
   // Tiles starting at t_lo .. t_hi - 1 (step TP) of the item; roff is the
   // offset of this network's part in the item's gradient row; MODE selects the
-  // epilogue (sInv: the LDS exchange area of the inverse problem).
-  template <bool PREFETCH_A, int MODE>
+  // epilogue (sInv: the LDS exchange area of the inverse problem); PHASE the
+  // parts run.  slot is this network's stash (slot_floats long).
+  template <bool PREFETCH_A, int MODE, int PHASE>
   __device__ __forceinline__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
-                                   float* slot, const float* sNb, float* sInv, int t_lo, int t_hi,
-                                   int roff) {
+                                   float* slot, int64_t slot_floats, const float* sNb, float* sInv, int t_lo,
+                                   int t_hi, int roff) {
     float* sW = lds;
     float* sA = sW + WP * WS + WP;   // after the staged weights and bias
     float* sH = sA + WP * TPS;
@@ -666,7 +673,7 @@ struct Tile {
                       : it.kind == KIND_AUX  ? ka.aux_xy
                                              : ka.if_xy;
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(slot, 0, (int)(ka.scratch_slot * sizeof(float)), 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(slot, 0, (int)(slot_floats * sizeof(float)), 0x00020000);
 
     for (int t0 = t_lo; t0 < t_hi; t0 += TP) {
       // lane indices re-derived per tile (see item_tid)
@@ -686,14 +693,16 @@ struct Tile {
         sX[TP + tp] = y;
       }
 
-      // ---- forward: Taylor streams through every layer, stash a^k
+      // ---- forward: Taylor streams through every layer, stash a^k (in PH_BWD
+      // only h^D is rebuilt, from the stashed a^D, or from layer 1 if D = 1)
       Streams H;
       {
         Streams A;
-        layer1(K, x, y, g, A);
+        if (PHASE == PH_BWD && D >= 2) stash_load(rs, 0, D - 2, wave, lane, A);
+        else layer1(K, x, y, g, A);
         activate(A, H);
       }
-      for (int k = 2; k <= D; ++k) {
+      for (int k = 2; k <= (PHASE == PH_BWD ? 1 : D); ++k) {
         tid = item_tid();
         lane = tid & 63;
         wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -713,7 +722,19 @@ struct Tile {
           for (int mb = 0; mb < MB; ++mb) H[st][mb] = Hn[st][mb];
       }
       float u[DO][4];
-      out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
+      if constexpr (PHASE == PH_BWD) {
+#pragma unroll
+        for (int c = 0; c < DO; ++c) u[c][0] = u[c][1] = u[c][2] = u[c][3] = 0.f;   // seeds come from LDS
+      } else {
+        out_fwd(K + L.k_out(), K + L.k_bout(), g, H, u);
+      }
+      if constexpr (PHASE == PH_FWD) {
+        if (g == 0) {
+#pragma unroll
+          for (int s = 0; s < 3; ++s) sInv[3 * tp + s] = u[0][s];
+        }
+        continue;
+      }
 
       // ---- loss terms and output seeds
       float ub[DO][4], loss[kLossTerms], kb[3];
@@ -960,10 +981,11 @@ struct Tile {
   // entry from a kernel built for classes up to WPMAX: the a^k prefetch costs
   // registers, so it is used for classes up to 48 in kernels that run two
   // waves per SIMD anyway because of a wider class
-  template <int WPMAX, int MODE>
+  template <int WPMAX, int MODE, int PHASE = PH_ALL>
   __device__ __forceinline__ static void train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* slot,
-                               const float* sNb, float* sInv, int t_lo, int t_hi, int roff) {
-    run_train<(WP <= 48 && WPMAX >= 48), MODE>(ka, it, nd, lds, slot, sNb, sInv, t_lo, t_hi, roff);
+                               int64_t slot_floats, const float* sNb, float* sInv, int t_lo, int t_hi, int roff) {
+    run_train<(WP <= 48 && WPMAX >= 48), MODE, PHASE>(ka, it, nd, lds, slot, slot_floats, sNb, sInv, t_lo, t_hi,
+                                                       roff);
   }
 };
 
@@ -1021,6 +1043,10 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
         nbu = ka.nets[it.side == 0 ? ifd.b_net : ifd.a_net];
         nbk = ka.nets[nbu.pair];
       }
+      // each network of the pair stashes into its own half of the slot: the
+      // K-network's forward (its streams to LDS) comes first, its reverse pass
+      // after the u-network's whole tile
+      const int64_t half = ka.scratch_slot / 2;
       for (int t0 = 0; t0 < it.count; t0 += TP) {
         __syncthreads();
         if (it.kind == KIND_IFACE) {
@@ -1029,11 +1055,12 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
           DDP_SWITCH(nbu.wclass, template values_tile<VAL_INV_NB>(ka, it, nbu, lds, sNb, sInv + 6 * TP, t0))
           __syncthreads();
         }
-        DDP_SWITCH(ndk.wclass, template values_tile<VAL_STREAMS>(ka, it, ndk, lds, sInv, nullptr, t0))
-        __syncthreads();
-        DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_INV_U>(ka, it, nd, lds, slot, sNb, sInv, t0, t0 + 1, 0))
-        DDP_SWITCH(ndk.wclass,
-                   template train<WPMAX, EPI_SEED>(ka, it, ndk, lds, slot, sNb, sInv, t0, t0 + 1, nd.gsize))
+        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_FWD>(ka, it, ndk, lds, slot + half, half, sNb,
+                                                                        sInv, t0, t0 + 1, nd.gsize))
+        DDP_SWITCH(nd.wclass,
+                   template train<WPMAX, EPI_INV_U>(ka, it, nd, lds, slot, half, sNb, sInv, t0, t0 + 1, 0))
+        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_BWD>(ka, it, ndk, lds, slot + half, half, sNb,
+                                                                        sInv, t0, t0 + 1, nd.gsize))
       }
       return;
     }
@@ -1044,7 +1071,9 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
     DDP_SWITCH(ndn.wclass, template values_tile<VAL_OWN>(ka, it, ndn, lds, sNb, nullptr, 0))
     __syncthreads();
   }
-  DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_OWN>(ka, it, nd, lds, slot, sNb, sInv, 0, it.count, 0))
+  DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_OWN>(ka, it, nd, lds, slot,
+                                                       PDE == PDE_INV ? ka.scratch_slot / 2 : ka.scratch_slot, sNb,
+                                                       sInv, 0, it.count, 0))
 #undef DDP_SWITCH
 #undef DDP_CASE
 }
@@ -1350,9 +1379,11 @@ size_t lds_bytes(int pde, int wpmax) {
   return (size_t)f;
 }
 
-int64_t scratch_slot_floats(int wpmax) {
-  // two regions (a^k and h^k) of kMaxDepth - 1 layers
-  return (int64_t)2 * (kMaxDepth - 1) * kWaves * 4 * (wpmax / 16) * 64 * 4;
+int64_t scratch_slot_floats(int pde, int wpmax) {
+  // two regions (a^k and h^k) of kMaxDepth - 1 layers; the inverse problem
+  // keeps one such stash per network of a pair
+  const int64_t one = (int64_t)2 * (kMaxDepth - 1) * kWaves * 4 * (wpmax / 16) * 64 * 4;
+  return pde == PDE_INV ? 2 * one : one;
 }
 
 hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream_t st) {
