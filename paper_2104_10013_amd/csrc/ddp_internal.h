@@ -138,7 +138,8 @@ struct RArgs {
   int* flags;                 // [0] non-finite loss seen
   int* tstate;
   int do_adam;
-  int* counter_reset;         // work counter to re-arm for the next train launch
+  int* counter_reset;         // work counters to re-arm for the next train launches
+  int n_counter_reset;
 };
 
 }  // namespace ddp

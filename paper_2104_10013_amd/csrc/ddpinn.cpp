@@ -89,7 +89,18 @@ struct ddp_problem {
   std::vector<int64_t> net_poff; // n_nets + 1: parameter offsets of networks
   int64_t kparam_floats = 0;
   int plan_slots = 512;          // workgroups the plan balances for
-  std::vector<Item> titems;      // train items (fused: descending cost; plain: grouped by q)
+  std::vector<Item> titems;      // train items (fused: descending cost per launch; plain: grouped by q)
+  // fused path: one persistent launch per kernel class the items need (items
+  // whose networks are all at most 80 wide run in a kernel that fits two
+  // waves per SIMD; items with a wider network in the widest class's kernel)
+  struct Launch {
+    int wpmax = 16;          // widest class of the launch's items
+    int begin = 0, count = 0;
+    int occupancy = 1;       // resident workgroups per CU of that kernel
+    int n_slots = 1;
+    int64_t slot_floats = 0;
+  };
+  std::vector<Launch> launches;
   std::vector<int> t_begin;      // per q ranges (plain path), n_sd + 1
   std::vector<IfaceDesc> ifaces;
   // gradient rows: CSR over networks (item index and offset of the network's
@@ -348,7 +359,48 @@ int build_plan(ddp_problem* p) {
     p->titems.insert(p->titems.end(), v.begin(), v.end());
   }
   p->t_begin[n_sd] = (int)p->titems.size();
-  if (p->fused) std::stable_sort(p->titems.begin(), p->titems.end(), by_cost);
+  // widest class an item's kernel must handle: its networks, its pair, and on
+  // an interface the neighbour's networks
+  auto need = [&](const Item& it) {
+    const NetDesc& n = p->nets[it.q];
+    int c = n.wclass;
+    const bool pair = n.pair >= 0 && (it.kind == KIND_RES || it.kind == KIND_IFACE);
+    if (pair) c = std::max(c, p->nets[n.pair].wclass);
+    if (it.kind == KIND_IFACE) {
+      const IfaceDesc& d = p->ifaces[it.iface];
+      const int nb = it.side == 0 ? d.b_net : d.a_net;
+      c = std::max(c, p->nets[nb].wclass);
+      if (p->nets[nb].pair >= 0) c = std::max(c, p->nets[p->nets[nb].pair].wclass);
+    }
+    return c;
+  };
+  p->launches.clear();
+  if (p->fused) {
+    std::vector<Item> narrow, wide;
+    int w_narrow = 16, w_wide = 16;
+    for (const Item& it : p->titems) {
+      const int c = need(it);
+      if (c <= 80) {
+        narrow.push_back(it);
+        w_narrow = std::max(w_narrow, c);
+      } else {
+        wide.push_back(it);
+        w_wide = std::max(w_wide, c);
+      }
+    }
+    std::stable_sort(narrow.begin(), narrow.end(), by_cost);
+    std::stable_sort(wide.begin(), wide.end(), by_cost);
+    p->titems.clear();
+    for (auto* grp : {&narrow, &wide}) {
+      if (grp->empty()) continue;
+      ddp_problem::Launch l;
+      l.wpmax = grp == &narrow ? w_narrow : w_wide;
+      l.begin = (int)p->titems.size();
+      l.count = (int)grp->size();
+      p->titems.insert(p->titems.end(), grp->begin(), grp->end());
+      p->launches.push_back(l);
+    }
+  }
   // partial rows and loss rows follow item order; a paired item's row holds
   // the u-network's part, then the K-network's
   auto paired = [&](const Item& it) {
@@ -457,19 +509,24 @@ int reduce_grid(ddp_problem* p, int q0, int q1) {
 int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, float* loss_out) {
   const int n_sd = (int)p->sds.size();
   if (p->fused) {
-    KArgs ka = make_kargs(p);
-    ka.items = p->d_titems;
-    ka.n_items = (int)p->titems.size();
-    ka.counter = p->d_counters;
-    ka.prologue = 1;
-    const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
-    HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, st));
+    for (size_t g = 0; g < p->launches.size(); ++g) {
+      const ddp_problem::Launch& l = p->launches[g];
+      KArgs ka = make_kargs(p);
+      ka.items = p->d_titems + l.begin;
+      ka.n_items = l.count;
+      ka.counter = p->d_counters + g;
+      ka.scratch_slot = l.slot_floats;
+      ka.prologue = g == 0;
+      const int grid = std::max(1, std::min(l.n_slots, l.count));
+      HIP_TRY(launch_train(p->pde, l.wpmax, ka, grid, st));
+    }
     RArgs ra = make_rargs(p);
     reduce_range(p, ra, 0, n_sd);
     ra.grad_out = grad_out;
     ra.loss_out = loss_out;
     ra.do_adam = do_adam;
     ra.counter_reset = p->d_counters;
+    ra.n_counter_reset = (int)p->launches.size();
     HIP_TRY(launch_reduce(ra, reduce_grid(p, 0, n_sd), st));
     return DDP_OK;
   }
@@ -479,7 +536,7 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     KArgs ka = make_kargs(p);
     ka.items = p->d_titems + p->t_begin[q];
     ka.n_items = p->t_begin[q + 1] - p->t_begin[q];
-    ka.counter = p->d_counters + 1 + q;
+    ka.counter = p->d_counters + p->launches.size() + q;
     ka.prologue = q == 0;
     if (ka.n_items == 0 && q != 0) continue;
     const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
@@ -491,7 +548,8 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     ra.grad_out = grad_out;
     ra.loss_out = loss_out;
     ra.do_adam = do_adam;
-    ra.counter_reset = p->d_counters + 1 + q;
+    ra.counter_reset = p->d_counters + p->launches.size() + q;
+    ra.n_counter_reset = 1;
     HIP_TRY(launch_reduce(ra, reduce_grid(p, q, q + 1), st));
   }
   return DDP_OK;
@@ -703,13 +761,23 @@ int install_plan(ddp_problem* p) {
   p->plan_slots = p->n_slots;
   if (int rc = build_plan(p)) return rc;
   p->slot_floats = scratch_slot_floats(p->pde, p->wpmax);
-  p->n_counters = n_sd + 1;
+  int64_t scratch_floats = (int64_t)p->n_slots * p->slot_floats;
+  for (ddp_problem::Launch& l : p->launches) {
+    HIP_TRY(train_occupancy(p->pde, l.wpmax, &l.occupancy));
+    if (l.occupancy < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
+    const int b = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, l.occupancy) : l.occupancy;
+    l.n_slots = std::max(1, p->n_cu * b);
+    l.slot_floats = scratch_slot_floats(p->pde, l.wpmax);
+    scratch_floats = std::max(scratch_floats, (int64_t)l.n_slots * l.slot_floats);
+  }
+  // counters: one per fused launch, then one per subdomain (plain path)
+  p->n_counters = (int)p->launches.size() + n_sd;
   int rc = 0;
   if ((rc = plan_upload(p, &p->d_counters, std::vector<int>(p->n_counters, 0)))) return rc;
   if ((rc = plan_upload(p, &p->d_titems, p->titems))) return rc;
   if ((rc = plan_alloc(p, &p->d_partial, (size_t)p->partial_floats))) return rc;
   if ((rc = plan_alloc(p, &p->d_loss_part, p->titems.size() * kLossTerms))) return rc;
-  if ((rc = plan_alloc(p, &p->d_scratch, (size_t)p->n_slots * p->slot_floats))) return rc;
+  if ((rc = plan_alloc(p, &p->d_scratch, (size_t)scratch_floats))) return rc;
   if ((rc = plan_upload(p, &p->d_net_row_ptr, p->net_row_ptr))) return rc;
   if ((rc = plan_upload(p, &p->d_row_prow, p->row_prow))) return rc;
   if ((rc = plan_upload(p, &p->d_sd_loss_ptr, p->sd_loss_ptr))) return rc;
@@ -839,11 +907,13 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
     hipEvent_t ev[2];
     HIP_TRY(hipEventCreate(&ev[0]));
     HIP_TRY(hipEventCreate(&ev[1]));
+    int max_occ = p->occupancy;   // the fused launches may run narrower kernels
+    for (const ddp_problem::Launch& l : p->launches) max_occ = std::max(max_occ, l.occupancy);
     const int64_t chunks[] = {256, 512, 1024, 2048};
     const int ipss[] = {1, 2, 4, 8};
     for (int64_t c : chunks) {
       for (int ips : ipss) {
-        for (int bpc = 1; bpc <= p->occupancy; ++bpc) {
+        for (int bpc = 1; bpc <= max_occ; ++bpc) {
           p->chunk_points = c;
           p->items_per_slot = ips;
           p->blocks_per_cu = bpc;
@@ -1004,17 +1074,29 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
     float total = 0.f;
     for (int i = 0; i < iters; ++i) {
       if (which == 0)
-        for (int c = 0; c <= n_sd; ++c) HIP_TRY(launch_reset_counter(p->d_counters + c, p->stream));
+        for (int c = 0; c < p->n_counters; ++c) HIP_TRY(launch_reset_counter(p->d_counters + c, p->stream));
       HIP_TRY(hipEventRecord(ev[0], p->stream));
       if (which == 0) {
-        for (int q = 0; q < (p->fused ? 1 : n_sd); ++q) {
+        const int nl = p->fused ? (int)p->launches.size() : n_sd;
+        for (int q = 0; q < nl; ++q) {
           KArgs ka = make_kargs(p);
-          ka.items = p->d_titems + (p->fused ? 0 : p->t_begin[q]);
-          ka.n_items = p->fused ? (int)p->titems.size() : p->t_begin[q + 1] - p->t_begin[q];
-          ka.counter = p->d_counters + (p->fused ? 0 : 1 + q);
+          int wpmax = p->wpmax, n_slots = p->n_slots;
+          if (p->fused) {
+            const ddp_problem::Launch& l = p->launches[q];
+            ka.items = p->d_titems + l.begin;
+            ka.n_items = l.count;
+            ka.counter = p->d_counters + q;
+            ka.scratch_slot = l.slot_floats;
+            wpmax = l.wpmax;
+            n_slots = l.n_slots;
+          } else {
+            ka.items = p->d_titems + p->t_begin[q];
+            ka.n_items = p->t_begin[q + 1] - p->t_begin[q];
+            ka.counter = p->d_counters + p->launches.size() + q;
+          }
           if (ka.n_items == 0) continue;
-          const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
-          HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, p->stream));
+          const int grid = std::max(1, std::min(n_slots, ka.n_items));
+          HIP_TRY(launch_train(p->pde, wpmax, ka, grid, p->stream));
         }
       } else {
         RArgs ra = make_rargs(p);
@@ -1031,7 +1113,7 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
     }
     ms[which] = total / iters;
   }
-  for (int c = 0; c <= n_sd; ++c) HIP_TRY(launch_reset_counter(p->d_counters + c, p->stream));
+  for (int c = 0; c < p->n_counters; ++c) HIP_TRY(launch_reset_counter(p->d_counters + c, p->stream));
   hipEventDestroy(ev[0]);
   hipEventDestroy(ev[1]);
   return DDP_OK;
@@ -1082,6 +1164,11 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   json_ints(f, "loss_rows", p->loss_rows);
   std::fprintf(f, ",\n");
   json_ints(f, "t_begin", p->t_begin);
+  std::fprintf(f, ",\n\"launches\": [");
+  for (size_t g = 0; g < p->launches.size(); ++g)
+    std::fprintf(f, "%s{\"wpmax\": %d, \"begin\": %d, \"count\": %d}", g ? ", " : "", p->launches[g].wpmax,
+                 p->launches[g].begin, p->launches[g].count);
+  std::fprintf(f, "]");
   std::fprintf(f,
                ",\n\"partial_floats\": %lld, \"n_res\": %zu, \"n_dat\": %zu, \"n_if\": %zu, \"n_aux\": %zu}\n",
                (long long)p->partial_floats, p->h_res_xy.size() / 2, p->h_dat_xy.size() / 2, p->h_if_xy.size() / 2,

@@ -1253,7 +1253,7 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
     }
     if (ra.do_adam && threadIdx.x == 0) ra.tstate[1] = 1;
     // the train kernel of this step has finished: re-arm its work counter
-    if (ra.counter_reset && threadIdx.x == 0) *ra.counter_reset = 0;
+    if (ra.counter_reset && (int)threadIdx.x < ra.n_counter_reset) ra.counter_reset[threadIdx.x] = 0;
   }
 }
 

@@ -68,9 +68,16 @@ def test_plan_covers_every_point_once(name, tmp_path):
         assert nets[row[0]]["sd"] == (e["a"] if row[5] == 0 else e["b"])
     for row in items[kind == 3]:
         assert nets[row[0]]["pair"] == -1 and nets[row[0] - 1]["pair"] == row[0]
-    # descending cost order (fused path)
+    # fused path: consecutive launches cover the items, descending cost within
+    # each; an item is in the narrow launch iff every network it runs is <= 80
     cost = [_item_cost(nets, a, b, c) for a, b, c in zip(q, kind, count)]
-    assert all(cost[i] >= cost[i + 1] for i in range(len(cost) - 1))
+    launches = d["launches"]
+    assert launches[0]["begin"] == 0 and sum(l["count"] for l in launches) == len(items)
+    for l in launches:
+        seg = cost[l["begin"]:l["begin"] + l["count"]]
+        assert all(seg[i] >= seg[i + 1] for i in range(len(seg) - 1))
+    for l in launches[1:]:
+        assert l["wpmax"] > 80 and launches[0]["wpmax"] <= 80
     # partial rows are disjoint, sized to the networks the item trains
     paired = np.array([nets[a]["pair"] >= 0 and b in (0, 2) for a, b in zip(q, kind)])
     size = np.array([nets[a]["gsize"] + (nets[nets[a]["pair"]]["gsize"] if pr else 0)
