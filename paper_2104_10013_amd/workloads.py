@@ -371,6 +371,80 @@ def burgers_exact(x, t, nu, n_nodes=120):
     return out
 
 
+def burgers_space_time(method, nx, nt, seed=0, scale=1.0, n_res=80000, width=20, depth=5,
+                       n_ic=256, n_bc=100, n_iface=20, lr=8e-4):
+    """The viscous Burgers problem of Sec. 7.5 (Eq. BE1: x in [-1,1], t in
+    [0,1], nu = 0.01/pi, u(0,x) = -sin(pi x), u(t,+-1) = 0) on an nx x nt grid
+    of space-time boxes, subdomain q = it * nx + ix.  Every subdomain has a
+    2-20x5-1 tanh network and learning rate 8e-4; the 80k residual points of
+    the whole domain are split evenly over the subdomains, and every common
+    edge carries 20 interface points (Sec. 7.5).  Space interfaces x = const
+    have normal (1, 0), time interfaces t = const normal (0, 1).  The 256
+    initial points are split evenly over the first time slab and the 100
+    points of each end line x = -1, +1 evenly over the time slabs.  Table 3
+    pairs cPINN with nt = 1 and XPINN with nt > 1; the flux of the cPINN
+    form is the space-time flux (u^2/2 - nu u_x, u), so a cPINN time
+    interface is defined as well.  Inputs are (x, t)."""
+    if nx < 1 or nt < 1:
+        raise ValueError("nx and nt must be positive")
+    g, p, w, _ = _streams(seed)
+    nu = 0.01 / math.pi
+    xs = np.linspace(-1.0, 1.0, nx + 1)
+    ts = np.linspace(0.0, 1.0, nt + 1)
+    per = lambda total, parts: max(1, int(round(total * scale / parts)))
+    n_r, n_0, n_b, n_i = per(n_res, nx * nt), per(n_ic, nx), per(n_bc, nt), per(n_iface, 1)
+    widths = [2] + [width] * depth + [1]
+    subs = []
+    for it in range(nt):
+        for ix in range(nx):
+            x0, x1, t0, t1 = xs[ix], xs[ix + 1], ts[it], ts[it + 1]
+            res = _box_points(p, n_r, x0, x1, t0, t1)
+            parts, targets = [np.zeros((0, 2))], [np.zeros(0)]
+            if it == 0:
+                ic = np.stack([p.uniform(x0, x1, n_0), np.zeros(n_0)], 1)
+                parts.append(ic)
+                targets.append(-np.sin(np.pi * ic[:, 0]))
+            for edge, on in ((-1.0, ix == 0), (1.0, ix == nx - 1)):
+                if on:
+                    parts.append(np.stack([np.full(n_b, edge), p.uniform(t0, t1, n_b)], 1))
+                    targets.append(np.zeros(n_b))
+            bnd = np.concatenate(parts, 0)
+            gv = np.concatenate(targets, 0)[:, None]
+            subs.append(Subdomain(widths=list(widths), loss_w=(1.0, 1.0, 1.0, 1.0), lr=lr,
+                                  res_xy=_f32(res), res_f=_f32(np.zeros((n_r, 1))),
+                                  bnd_xy=_f32(bnd), bnd_g=_f32(gv),
+                                  params=glorot_params(w, widths)))
+    ifaces = []
+    for it in range(nt):
+        for ix in range(nx):
+            q = it * nx + ix
+            if ix + 1 < nx:   # space interface x = xs[ix+1], open in t
+                pts = _segment_points(p, n_i, (xs[ix + 1], ts[it]), (xs[ix + 1], ts[it + 1]))
+                ifaces.append(Interface(q, q + 1, _f32(pts), _f32([1.0, 0.0])))
+            if it + 1 < nt:   # time interface t = ts[it+1], open in x
+                pts = _segment_points(p, n_i, (xs[ix], ts[it + 1]), (xs[ix + 1], ts[it + 1]))
+                ifaces.append(Interface(q, q + nx, _f32(pts), _f32([0.0, 1.0])))
+    gx = np.linspace(-1.0, 1.0, 256)
+    gt = np.linspace(0.0, 1.0, 101)
+    X, T = np.meshgrid(gx, gt, indexing="ij")
+    exy32 = _f32(np.stack([X.ravel(), T.ravel()], 1))
+    ex = exy32.astype(np.float64)
+    owner = -np.ones((len(ex), 4), np.int32)
+    cnt = np.zeros(len(ex), np.int32)
+    for it in range(nt):
+        for ix in range(nx):
+            inside = ((ex[:, 0] >= xs[ix]) & (ex[:, 0] <= xs[ix + 1]) &
+                      (ex[:, 1] >= ts[it]) & (ex[:, 1] <= ts[it + 1]))
+            idx = np.nonzero(inside)[0]
+            owner[idx, cnt[idx]] = it * nx + ix
+            cnt[idx] += 1
+    exact = burgers_exact(ex[:, 0], ex[:, 1], nu)[:, None]
+    name = f"burgers_{method}_{nx}x{nt}"
+    return Problem(name=name, method=method, pde=PDE_BURGERS1D, coef=(nu,), subdomains=subs,
+                   interfaces=ifaces, eval_xy=exy32, eval_owner=owner, eval_exact=exact,
+                   meta={"nx": nx, "nt": nt})
+
+
 def c4_xpinn_kovasznay(seed=0, scale=1.0, re=40.0):
     """XPINN, steady NS (Eq. NSEq) at Re = 40 with the Kovasznay closed form on
     [-0.5,1] x [-0.5,1.5], 3x3 subdomains, nets 2-60x5-3, 10k residual points
@@ -539,6 +613,22 @@ WORKLOADS = {
     "c4_xpinn_kovasznay": c4_xpinn_kovasznay,
     "c5_xpinn_inverse_diffusion": c5_xpinn_inverse_diffusion,
 }
+
+#: the space-time Burgers partitions of Table 3 (cPINN in space only, XPINN in
+#: space and time), 80k residual points in every case
+TABLE3_PARTITIONS = (("cpinn", 4, 1), ("cpinn", 8, 1), ("cpinn", 16, 1), ("cpinn", 32, 1),
+                     ("xpinn", 2, 2), ("xpinn", 4, 2), ("xpinn", 4, 4), ("xpinn", 8, 4))
+
+
+def _table3_entry(method, nx, nt):
+    def make(seed=0, scale=1.0):
+        return burgers_space_time(method, nx, nt, seed=seed, scale=scale)
+    make.__name__ = f"burgers_st_{method}_{nx}x{nt}"
+    return make
+
+
+for _m, _nx, _nt in TABLE3_PARTITIONS:
+    WORKLOADS[f"burgers_st_{_m}_{_nx}x{_nt}"] = _table3_entry(_m, _nx, _nt)
 
 
 def make_problem(name, seed=0, scale=1.0, **kw):

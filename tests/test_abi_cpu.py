@@ -43,7 +43,7 @@ def _item_cost(nets, q, kind, count):
 
 
 @pytest.mark.parametrize("name", ["c1_cpinn_poisson", "c2_xpinn_poisson", "c3_cpinn_burgers", "c4_xpinn_kovasznay",
-                                  "c5_xpinn_inverse_diffusion"])
+                                  "c5_xpinn_inverse_diffusion", "burgers_st_xpinn_4x4", "burgers_st_cpinn_32x1"])
 def test_plan_covers_every_point_once(name, tmp_path):
     prob = W.make_problem(name, seed=0, scale=0.05 if name.startswith("c5") else 0.3)
     d = _plan(prob, tmp_path, chunk_points=100)

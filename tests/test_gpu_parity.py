@@ -401,3 +401,40 @@ def test_c5_training_trajectory_loosely_follows_oracle():
     _, hist_ref = oracle.train(prob, [s.params for s in prob.subdomains], n)
     np.testing.assert_allclose(hist[:, :, 0], hist_ref[:, :, 0], rtol=2e-3)
     pb.close()
+
+
+@pytest.mark.parametrize("method,nx,nt", W.TABLE3_PARTITIONS)
+def test_space_time_burgers_partitions_full_size(method, nx, nt):
+    """Every space-time partition of the viscous Burgers comparison (80k
+    residual points, 2-20x5-1 networks), at init and perturbed; the 4 x 4
+    XPINN and 16-strip cPINN cases also in the autotuned plan and the plain
+    path."""
+    prob = W.make_problem(f"burgers_st_{method}_{nx}x{nt}", seed=0)
+    variants = [(None, True, False)]
+    if (method, nx, nt) in (("xpinn", 4, 4), ("cpinn", 16, 1)):
+        variants += [(61, True, True), (61, False, False)]
+    for seed, fused, tuned in variants:
+        params = _params(prob, seed)
+        _say(f"burgers {method} {nx}x{nt} perturbation {seed} fused {fused} autotuned {tuned}")
+        pb = ddpinn.Problem(prob, fused=fused)
+        pb.set_params(params)
+        if tuned:
+            _say(f"  plan {pb.autotune(iters=3)}")
+        lt, g = pb.loss_and_grad()
+        torch.cuda.synchronize()
+        wl, wg = compare(prob, params, lt.cpu().numpy(), [x.cpu().numpy() for x in pb.split(g.cpu())])
+        _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+        pb.close()
+
+
+def test_space_time_burgers_training_trajectory_loosely_follows_oracle():
+    """20 Adam steps of the 2 x 2 space-time XPINN case at a fifth of its
+    points: the per-subdomain losses follow the FP64 oracle's trajectory."""
+    prob = W.burgers_space_time("xpinn", 2, 2, seed=2, scale=0.2)
+    n = 20
+    _say("burgers space-time trajectory 20 steps")
+    pb = ddpinn.Problem(prob, fused=True)
+    hist = np.stack([pb.step(1).cpu().numpy().copy() for _ in range(n)])
+    _, hist_ref = oracle.train(prob, [s.params for s in prob.subdomains], n)
+    np.testing.assert_allclose(hist[:, :, 0], hist_ref[:, :, 0], rtol=1e-3)
+    pb.close()

@@ -487,3 +487,72 @@ def test_subdomain_without_points_has_zero_loss_and_gradient():
     terms, grads = O.loss_and_grad(prob, [s.params for s in prob.subdomains])
     assert np.all(terms[1] == 0) and np.all(grads[1] == 0) and grads[1].shape == prob.subdomains[1].params.shape
     assert terms[0, 2] > 0 and np.linalg.norm(grads[0]) > 0
+
+
+# --------------------------------------------------------------------------
+# space-time decomposition of the viscous Burgers problem (Sec. 7.5)
+
+
+def _tiny_space_time(method, nx, nt, widths=(2, 3, 3, 1), seed=2):
+    prob = W.burgers_space_time(method, nx, nt, seed=seed, scale=0.0004, n_iface=300)
+    rng = np.random.default_rng(seed)
+    for s in prob.subdomains:
+        s.widths = list(widths)
+        s.params = _rand_theta(rng, s.widths).numpy().astype(np.float32)
+    return prob
+
+
+def _net(prob, params, q, z):
+    return O.mlp(torch.tensor(params[q], dtype=DT), prob.subdomains[q].widths, z)[:, 0]
+
+
+def test_space_time_xpinn_burgers_gradient_vs_central_fd():
+    """2 x 2 space-time boxes: subdomain 0 has initial, boundary, a space and
+    a time interface; subdomain 3 a space and a time interface from the other
+    side."""
+    prob = _tiny_space_time("xpinn", 2, 2)
+    assert sorted(tuple(e.normal) for e in prob.interfaces) == [(0.0, 1.0), (0.0, 1.0), (1.0, 0.0), (1.0, 0.0)]
+    params = [W.perturb_params(s.params, 6, 0.3) for s in prob.subdomains]
+    _, grads = O.loss_and_grad(prob, params)
+    for q in (0, 3):
+        np.testing.assert_allclose(grads[q], _fd_grad(prob, params, q), rtol=2e-6, atol=1e-8)
+
+
+def test_cpinn_time_interface_flux_is_the_jump_of_u():
+    """Across t = const the normal (0, 1) picks the time component u of the
+    space-time flux (u^2/2 - nu u_x, u): the flux term is the mean squared
+    jump of u, four times the average-solution term, whatever nu and u_x."""
+    prob = _tiny_space_time("cpinn", 1, 2)
+    params = [s.params for s in prob.subdomains]
+    (e,) = prob.interfaces
+    z = torch.tensor(e.xy, dtype=DT)
+    jump2 = float(((_net(prob, params, 0, z) - _net(prob, params, 1, z)) ** 2).mean())
+    terms, _ = O.loss_and_grad(prob, params)
+    for q in range(2):
+        assert terms[q, 4] == pytest.approx(jump2, rel=1e-12)
+        assert terms[q, 3] == pytest.approx(jump2 / 4, rel=1e-12)
+
+
+def test_xpinn_time_interface_residual_continuity_by_fd():
+    """XPINN residual continuity on a time interface: the mean squared jump of
+    u_t + u u_x - nu u_xx between the two networks, the derivatives taken by
+    central differences of the networks in (x, t)."""
+    prob = _tiny_space_time("xpinn", 1, 2, widths=(2, 5, 5, 1))
+    params = [W.perturb_params(s.params, 3, 0.2) for s in prob.subdomains]
+    (e,) = prob.interfaces
+    nu = prob.coef[0]
+    z = torch.tensor(e.xy, dtype=DT)
+
+    def burgers_fd(q):
+        u = lambda dz: _net(prob, params, q, z + torch.tensor(dz, dtype=DT))
+        h1, h2 = 1e-5, 1e-3
+        ut = (u([0, h1]) - u([0, -h1])) / (2 * h1)
+        ux = (u([h1, 0]) - u([-h1, 0])) / (2 * h1)
+        uxx = (u([h2, 0]) - 2 * u([0, 0]) + u([-h2, 0])) / h2 ** 2
+        return ut + u([0, 0]) * ux - nu * uxx
+
+    ref = float(((burgers_fd(0) - burgers_fd(1)) ** 2).mean())
+    terms, _ = O.loss_and_grad(prob, params)
+    assert ref > 0
+    for q in range(2):
+        assert terms[q, 4] == pytest.approx(ref, rel=1e-5)

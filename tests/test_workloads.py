@@ -1,0 +1,69 @@
+"""Host checks of the space-time Burgers inputs (Sec. 7.5, Table 3): every
+point lies where its role says, the counts add up to the paper's totals, and
+every subdomain / interface is present once."""
+import numpy as np
+import pytest
+
+from paper_2104_10013_amd import workloads as W
+
+
+@pytest.mark.parametrize("method,nx,nt", W.TABLE3_PARTITIONS)
+def test_space_time_burgers_geometry(method, nx, nt):
+    prob = W.make_problem(f"burgers_st_{method}_{nx}x{nt}", seed=0)
+    xs, ts = np.linspace(-1, 1, nx + 1), np.linspace(0, 1, nt + 1)
+    assert prob.n_sd == nx * nt and prob.method == method and prob.pde == W.PDE_BURGERS1D
+    assert prob.coef[0] == pytest.approx(0.01 / np.pi)
+    assert abs(prob.n_residual() - 80000) <= nx * nt
+    tol = 1e-6
+    n_ic = n_bc = 0
+    for q, s in enumerate(prob.subdomains):
+        ix, it = q % nx, q // nx
+        assert s.widths == [2] + [20] * 5 + [1] and s.lr == pytest.approx(8e-4)
+        assert s.params.size == W.param_count(s.widths)
+        r = s.res_xy.astype(np.float64)
+        assert (r[:, 0] >= xs[ix] - tol).all() and (r[:, 0] <= xs[ix + 1] + tol).all()
+        assert (r[:, 1] >= ts[it] - tol).all() and (r[:, 1] <= ts[it + 1] + tol).all()
+        assert np.all(s.res_f == 0)
+        b, g = s.bnd_xy.astype(np.float64), s.bnd_g[:, 0].astype(np.float64)
+        ic = b[:, 1] == 0
+        bc = np.abs(b[:, 0]) == 1
+        assert np.all(ic | bc)
+        if it > 0:
+            assert not ic.any()
+        if 0 < ix < nx - 1:
+            assert not bc.any()
+        np.testing.assert_allclose(g[ic], -np.sin(np.pi * b[ic, 0]), atol=1e-6)
+        assert np.all(g[bc & ~ic] == 0)
+        n_ic += int(ic.sum())
+        n_bc += int(bc.sum())
+    assert abs(n_ic - 256) <= nx and abs(n_bc - 200) <= 2 * nt
+    # one interface per common edge, 20 points in its open segment
+    assert len(prob.interfaces) == (nx - 1) * nt + nx * (nt - 1)
+    seen = set()
+    for e in prob.interfaces:
+        assert (e.a, e.b) not in seen
+        seen.add((e.a, e.b))
+        xy = e.xy.astype(np.float64)
+        assert len(xy) == 20
+        ax, at, bx, bt = e.a % nx, e.a // nx, e.b % nx, e.b // nx
+        if tuple(e.normal) == (1.0, 0.0):
+            assert (bx, bt) == (ax + 1, at)
+            assert np.allclose(xy[:, 0], xs[ax + 1], atol=tol)
+            assert (xy[:, 1] > ts[at]).all() and (xy[:, 1] < ts[at + 1]).all()
+        else:
+            assert tuple(e.normal) == (0.0, 1.0) and (bx, bt) == (ax, at + 1)
+            assert np.allclose(xy[:, 1], ts[at + 1], atol=tol)
+            assert (xy[:, 0] > xs[ax]).all() and (xy[:, 0] < xs[ax + 1]).all()
+    # evaluation grid: every point owned, cross points by four subdomains
+    own = (prob.eval_owner >= 0).sum(1)
+    assert own.min() >= 1 and own.max() <= 4
+    assert prob.eval_exact.shape == (256 * 101, 1)
+
+
+def test_space_time_burgers_is_seeded():
+    a = W.burgers_space_time("xpinn", 4, 2, seed=3, scale=0.1)
+    b = W.burgers_space_time("xpinn", 4, 2, seed=3, scale=0.1)
+    c = W.burgers_space_time("xpinn", 4, 2, seed=4, scale=0.1)
+    assert all(np.array_equal(s.res_xy, t.res_xy) and np.array_equal(s.params, t.params)
+               for s, t in zip(a.subdomains, b.subdomains))
+    assert not np.array_equal(a.subdomains[0].res_xy, c.subdomains[0].res_xy)
