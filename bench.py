@@ -28,25 +28,25 @@ def algorithmic_flops(prob):
     """MFMA-countable work of one step: the hidden-to-hidden products
     (unpadded widths), forward (2 flops per MAC) plus the two backward
     contractions (g = W^T abar and dW), times the Taylor streams each point
-    class carries: residual 4, data 1, interface 4 (XPINN) or 2 (cPINN) per
-    network evaluating it."""
-    s_if = 4 if prob.method == "xpinn" else 2
-    n_if = [0] * prob.n_sd
+    class carries: residual 4, data 1, interface 4 (XPINN) or 2 (cPINN: value
+    and normal derivative) per network evaluating it."""
+    n_if = [0] * prob.n_sd   # interface stream-points per subdomain
     for e in prob.interfaces:
-        n_if[e.a] += e.xy.shape[0]
-        n_if[e.b] += e.xy.shape[0]
+        s_if = 4 if (getattr(e, "method", None) or prob.method) == "xpinn" else 2
+        n_if[e.a] += s_if * e.xy.shape[0]
+        n_if[e.b] += s_if * e.xy.shape[0]
     total = 0.0
     for q, s in enumerate(prob.subdomains):
         w = s.widths[1]
         depth = len(s.widths) - 2
-        cols = 4 * s.res_xy.shape[0] + 1 * s.bnd_xy.shape[0] + s_if * n_if[q]
+        cols = 4 * s.res_xy.shape[0] + 1 * s.bnd_xy.shape[0] + n_if[q]
         total += 6.0 * cols * (depth - 1) * w * w
         if s.aux_widths is not None:
             # conductivity network of the inverse problem: value and gradient
             # streams where the residual or the interface needs them, value at
             # its data points
             wk, dk = s.aux_widths[1], len(s.aux_widths) - 2
-            colk = 3 * s.res_xy.shape[0] + 1 * s.aux_xy.shape[0] + 3 * n_if[q]
+            colk = 3 * s.res_xy.shape[0] + 1 * s.aux_xy.shape[0] + 3 * n_if[q] // 4
             total += 6.0 * colk * (dk - 1) * wk * wk
     return total
 

@@ -49,7 +49,13 @@ enum {
 };
 
 /* Algorithm 1 selects the interface condition: cPINN (normal-flux continuity)
- * or XPINN (residual continuity); both add average-solution continuity. */
+ * or XPINN (residual continuity); both add average-solution continuity.
+ * Normal fluxes f(u) . n of the conservative forms:
+ *  POISSON2D    f = -grad u.
+ *  BURGERS1D    the space-time flux (u^2/2 - nu u_x, u) in (x, t).
+ *  NS2D_STEADY  Table 1: x-momentum (u^2 + p - u_x/Re, uv - u_y/Re),
+ *               y-momentum (uv - v_x/Re, v^2 + p - v_y/Re), mass (u, v); the
+ *               three squared jumps are summed. */
 enum { DDP_CPINN = 0, DDP_XPINN = 1 };
 
 /* Operators L_x of Eq. ProSet (F = L_x(u) - f):
@@ -76,7 +82,9 @@ enum {
 };
 
 /* Create an empty problem.  coef holds n_coef operator constants (see the
- * operator list above).  method is DDP_CPINN or DDP_XPINN. */
+ * operator list above).  method is DDP_CPINN or DDP_XPINN: the interface
+ * condition of every interface unless ddp_set_interface_method overrides it
+ * (DDP_DIFFUSION2D_INV: XPINN only). */
 int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n_coef);
 
 /* Add subdomain Omega_q with its network (Sec. 3).  n_nets is 1, or 2 for
@@ -106,6 +114,16 @@ int ddp_set_points(ddp_problem* p, int sd, int kind, int n, const float* xy, con
 int ddp_add_interface(ddp_problem* p, int sd_a, int sd_b, int n, const float* xy,
                       const float normal[2], int on_device, int* if_id);
 
+/* Give interface if_id its own condition, DDP_CPINN (flux matching) or
+ * DDP_XPINN (residual continuity), instead of the problem's: e.g. cPINN
+ * across space interfaces and XPINN across time interfaces of a time-dependent
+ * conservation law, the combination the paper's conclusions propose.  The
+ * fourth loss term of a subdomain (weight loss_w[3], slot 4 of loss_terms) then
+ * sums the flux terms of its cPINN interfaces and the residual terms of its
+ * XPINN interfaces.  DDP_EINVAL for an unknown interface or method, or
+ * DDP_CPINN on DDP_DIFFUSION2D_INV.  Valid before ddp_finalize. */
+int ddp_set_interface_method(ddp_problem* p, int if_id, int method);
+
 /* Set a tuning option (see DDP_OPT_*).  Valid before ddp_finalize. */
 int ddp_set_option(ddp_problem* p, int option, int64_t value);
 
@@ -119,10 +137,11 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused);
 
 /* Autotuner: time candidate work plans on this problem (points per item
  * bound 256..2048, items per resident workgroup 1..8, workgroups per compute
- * unit 1..as many as fit) with iters loss-and-gradient passes each, keep the
+ * unit 1..as many as fit) with iters loss-and-gradient passes each, time the
+ * three fastest again (three interleaved rounds of 2 x iters passes), keep the
  * fastest and rebuild the step graph with it.  Parameters and Adam state are
  * not changed.  cache_path (may be NULL) is a JSON-lines file of earlier
- * choices keyed by a signature of the problem (operator, method, fused or
+ * choices keyed by a signature of the problem (operator, interface methods, fused or
  * per-subdomain path, widths, depths, point counts, CU count): a hit skips
  * the search, a miss appends the new choice.  choice (may be NULL) receives
  * the 3 chosen values.  Not safe to call while the caller's stream runs other

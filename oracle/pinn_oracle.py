@@ -146,10 +146,15 @@ def split_theta(prob, q, theta):
 
 
 def normal_flux(pde, coef, st, n):
-    """f(u) . n for the conservative form of the equation, shape (N, 1).
+    """f(u) . n for the conservative form of the equation, shape (N, n_eq).
 
     Poisson:  f = -grad u.
     Burgers:  space-time flux (u^2/2 - nu u_x, u) of u_t + (u^2/2 - nu u_x)_x = 0.
+    NS:       the x-momentum, y-momentum and mass fluxes of Table 1, with
+              (x, y) components
+              (u^2 + p - u_x/Re, uv - u_y/Re),
+              (uv - v_x/Re, v^2 + p - v_y/Re),
+              (u, v).
     """
     u, du = st["u"], st["du"]
     if pde == POISSON2D:
@@ -158,6 +163,13 @@ def normal_flux(pde, coef, st, n):
         nu = coef[0]
         fx = 0.5 * u[:, 0] ** 2 - nu * du[:, 0, 0]
         return (n[0] * fx + n[1] * u[:, 0])[:, None]
+    if pde == NS2D:
+        re = coef[0]
+        U, V, P = u[:, 0], u[:, 1], u[:, 2]
+        mx = n[0] * (U * U + P - du[:, 0, 0] / re) + n[1] * (U * V - du[:, 0, 1] / re)
+        my = n[0] * (U * V - du[:, 1, 0] / re) + n[1] * (V * V + P - du[:, 1, 1] / re)
+        ms = n[0] * U + n[1] * V
+        return torch.stack([mx, my, ms], 1)
     raise NotImplementedError(f"cPINN flux for {pde}")
 
 
@@ -176,14 +188,22 @@ def _mean_sq(x):
     return (x ** 2).sum() / x.shape[0]
 
 
+def interface_method(prob, e):
+    """The interface condition of e: its own method where one is set (the
+    cPINN-in-space, XPINN-in-time combination of the conclusions), else the
+    problem's."""
+    return getattr(e, "method", None) or prob.method
+
+
 def interface_value(prob, q, theta, e, create_graph):
     """What subdomain q contributes on interface e: u, and flux.n (cPINN) or F (XPINN)."""
     sd = prob.subdomains[q]
     z = _t(e.xy)
+    method = interface_method(prob, e)
     if prob.pde == DIFF_INV:
         # the pair (u, K) is the solution whose average is matched; the
         # operator value L(u, K) = div(K grad u) is compared (f cancels)
-        if prob.method != "xpinn":
+        if method != "xpinn":
             raise NotImplementedError("the inverse problem uses XPINN interfaces")
         thu, thk = split_theta(prob, q, theta)
         stu = input_streams(thu, sd.widths, z, prob.pde, create_graph=create_graph)
@@ -192,7 +212,7 @@ def interface_value(prob, q, theta, e, create_graph):
         return torch.cat([stu["u"], stk["u"]], 1), residual_inverse(stu, stk, f0)
     st = input_streams(theta, sd.widths, z, prob.pde, create_graph=create_graph)
     u = st["u"]
-    if prob.method == "cpinn":
+    if method == "cpinn":
         other = normal_flux(prob.pde, prob.coef, st, _t(e.normal))
     else:
         # the forcing f is the same on both sides of a common point and cancels

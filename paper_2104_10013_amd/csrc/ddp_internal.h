@@ -88,6 +88,7 @@ struct IfaceDesc {
   int a_net, b_net; // their (u-)networks
   int begin, count; // range in the packed interface point array
   float nx, ny;
+  int method;       // interface condition: METHOD_CPINN flux matching or METHOD_XPINN residual continuity
 };
 
 // Arguments of the per-point kernels.
@@ -110,7 +111,6 @@ struct KArgs {
   int64_t scratch_slot;   // floats per workgroup slot
   int* counter;           // work counter of this launch (zero at launch)
   int* tstate;            // [0] completed Adam steps, [1] pending increment
-  int method;
   int n_eq;
   float coef0;
   int prologue;           // 1: block 0 settles the Adam step counter

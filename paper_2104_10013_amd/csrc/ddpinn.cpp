@@ -51,6 +51,7 @@ struct HostIf {
   int a, b, n;
   std::vector<float> xy;
   float nx, ny;
+  int method = -1;   // interface condition; -1: the problem's method
 };
 
 template <class T>
@@ -283,6 +284,7 @@ int build_plan(ddp_problem* p) {
     d.count = f.n;
     d.nx = f.nx;
     d.ny = f.ny;
+    d.method = f.method >= 0 ? f.method : p->method;
     p->h_if_xy.insert(p->h_if_xy.end(), f.xy.begin(), f.xy.end());
     p->ifaces.push_back(d);
   }
@@ -466,7 +468,6 @@ KArgs make_kargs(ddp_problem* p) {
   ka.scratch = p->d_scratch;
   ka.scratch_slot = p->slot_floats;
   ka.tstate = p->d_tstate;
-  ka.method = p->method;
   ka.n_eq = p->n_eq;
   ka.coef0 = (float)p->coef[0];
   return ka;
@@ -605,8 +606,6 @@ int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n
     return fail(DDP_EINVAL, "operator needs coef[0] (nu or Re)");
   for (int i = 0; i < n_coef; ++i)
     if (!std::isfinite(coef[i]) || coef[i] <= 0) return fail(DDP_EINVAL, "coefficients must be finite and > 0");
-  if (method == DDP_CPINN && pde == DDP_NS2D_STEADY)
-    return fail(DDP_EINVAL, "cPINN flux terms are not provided for Navier-Stokes; use DDP_XPINN");
   if (method == DDP_CPINN && pde == DDP_DIFFUSION2D_INV)
     return fail(DDP_EINVAL, "the inverse diffusion problem uses XPINN interfaces");
   ddp_problem* p = new (std::nothrow) ddp_problem();
@@ -709,6 +708,17 @@ int ddp_add_interface(ddp_problem* p, int sd_a, int sd_b, int n, const float* xy
   if (!all_finite(f.xy.data(), f.xy.size())) return fail(DDP_EINVAL, "non-finite coordinate");
   p->ifs.push_back(std::move(f));
   if (if_id) *if_id = (int)p->ifs.size() - 1;
+  p->planned = false;
+  return DDP_OK;
+}
+
+int ddp_set_interface_method(ddp_problem* p, int if_id, int method) {
+  if (int rc = check_open(p)) return rc;
+  if (if_id < 0 || if_id >= (int)p->ifs.size()) return fail(DDP_EINVAL, "unknown interface");
+  if (method != DDP_CPINN && method != DDP_XPINN) return fail(DDP_EINVAL, "method must be DDP_CPINN or DDP_XPINN");
+  if (method == DDP_CPINN && p->pde == DDP_DIFFUSION2D_INV)
+    return fail(DDP_EINVAL, "the inverse diffusion problem uses XPINN interfaces");
+  p->ifs[if_id].method = method;
   p->planned = false;
   return DDP_OK;
 }
@@ -829,6 +839,7 @@ uint64_t problem_signature(const ddp_problem* p) {
     mix(f.a);
     mix(f.b);
     mix(f.n);
+    mix(f.method >= 0 ? f.method : p->method);
   }
   return h;
 }
@@ -911,32 +922,55 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
     for (const ddp_problem::Launch& l : p->launches) max_occ = std::max(max_occ, l.occupancy);
     const int64_t chunks[] = {256, 512, 1024, 2048};
     const int ipss[] = {1, 2, 4, 8};
-    for (int64_t c : chunks) {
-      for (int ips : ipss) {
+    struct Cand {
+      int64_t c;
+      int ips, bpc;
+      float ms;
+    };
+    std::vector<Cand> cands;
+    // mean time of one loss + gradient pass (no Adam) of candidate k over n
+    // passes, after one untimed pass
+    auto time_cand = [&](const Cand& k, int n, float* ms) -> int {
+      p->chunk_points = k.c;
+      p->items_per_slot = k.ips;
+      p->blocks_per_cu = k.bpc;
+      if (int rc = install_plan(p)) return rc;
+      if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
+      HIP_TRY(hipEventRecord(ev[0], p->stream));
+      for (int i = 0; i < n; ++i)
+        if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
+      HIP_TRY(hipEventRecord(ev[1], p->stream));
+      HIP_TRY(hipEventSynchronize(ev[1]));
+      HIP_TRY(hipEventElapsedTime(ms, ev[0], ev[1]));
+      *ms /= n;
+      return DDP_OK;
+    };
+    for (int64_t c : chunks)
+      for (int ips : ipss)
         for (int bpc = 1; bpc <= max_occ; ++bpc) {
-          p->chunk_points = c;
-          p->items_per_slot = ips;
-          p->blocks_per_cu = bpc;
-          if (int rc = install_plan(p)) return rc;
-          // one untimed pass, then the timed passes (loss + gradient, no Adam)
-          if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
-          HIP_TRY(hipEventRecord(ev[0], p->stream));
-          for (int i = 0; i < iters; ++i)
-            if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
-          HIP_TRY(hipEventRecord(ev[1], p->stream));
-          HIP_TRY(hipEventSynchronize(ev[1]));
-          float ms = 0.f;
-          HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
-          ms /= iters;
-          if (ms < best_ms) {
-            best_ms = ms;
-            best[0] = c;
-            best[1] = ips;
-            best[2] = bpc;
-          }
+          Cand k{c, ips, bpc, 0.f};
+          if (int rc = time_cand(k, iters, &k.ms)) return rc;
+          cands.push_back(k);
         }
+    // the leading candidates are often within a percent of each other: time the
+    // best three again, interleaved over three rounds of 2 x iters passes, and
+    // keep the smallest total
+    std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+    const int n_final = std::min<int>(3, (int)cands.size());
+    std::vector<float> total(n_final, 0.f);
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < n_final; ++k) {
+        float ms = 0.f;
+        if (int rc = time_cand(cands[k], 2 * iters, &ms)) return rc;
+        total[k] += ms;
       }
-    }
+    for (int k = 0; k < n_final; ++k)
+      if (total[k] / 3 < best_ms) {
+        best_ms = total[k] / 3;
+        best[0] = cands[k].c;
+        best[1] = cands[k].ips;
+        best[2] = cands[k].bpc;
+      }
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
     (void)n_sd;
@@ -1138,8 +1172,8 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   std::fprintf(f, "],\n\"ifaces\": [");
   for (size_t e = 0; e < p->ifaces.size(); ++e) {
     const IfaceDesc& d = p->ifaces[e];
-    std::fprintf(f, "%s{\"a\": %d, \"b\": %d, \"begin\": %d, \"count\": %d}", e ? ", " : "", d.a, d.b, d.begin,
-                 d.count);
+    std::fprintf(f, "%s{\"a\": %d, \"b\": %d, \"begin\": %d, \"count\": %d, \"method\": %d}", e ? ", " : "", d.a,
+                 d.b, d.begin, d.count, d.method);
   }
   auto items = [&](const char* name, const std::vector<Item>& v) {
     std::fprintf(f, "],\n\"%s\": [", name);

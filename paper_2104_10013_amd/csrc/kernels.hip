@@ -158,13 +158,13 @@ template <> struct Op<PDE_POISSON> {
                                       float (&ub)[DO][4]) {
     ub[0][3] -= c[0];
   }
-  __device__ static float flux(const float (&u)[DO][4], float nx, float ny, float coef) {
-    return -(nx * u[0][1] + ny * u[0][2]);
+  __device__ static void flux(const float (&u)[DO][4], float nx, float ny, float coef, float (&fl)[NEQ]) {
+    fl[0] = -(nx * u[0][1] + ny * u[0][2]);
   }
-  __device__ static void flux_adj(const float (&u)[DO][4], float nx, float ny, float coef, float c,
+  __device__ static void flux_adj(const float (&u)[DO][4], float nx, float ny, float coef, const float (&c)[NEQ],
                                   float (&ub)[DO][4]) {
-    ub[0][1] -= c * nx;
-    ub[0][2] -= c * ny;
+    ub[0][1] -= c[0] * nx;
+    ub[0][2] -= c[0] * ny;
   }
 };
 
@@ -182,17 +182,19 @@ template <> struct Op<PDE_BURGERS> {
     ub[0][1] += c[0] * u[0][0];
     ub[0][3] -= nu * c[0];
   }
-  __device__ static float flux(const float (&u)[DO][4], float nx, float ny, float nu) {
-    return nx * (0.5f * u[0][0] * u[0][0] - nu * u[0][1]) + ny * u[0][0];
+  __device__ static void flux(const float (&u)[DO][4], float nx, float ny, float nu, float (&fl)[NEQ]) {
+    fl[0] = nx * (0.5f * u[0][0] * u[0][0] - nu * u[0][1]) + ny * u[0][0];
   }
-  __device__ static void flux_adj(const float (&u)[DO][4], float nx, float ny, float nu, float c,
+  __device__ static void flux_adj(const float (&u)[DO][4], float nx, float ny, float nu, const float (&c)[NEQ],
                                   float (&ub)[DO][4]) {
-    ub[0][0] += c * (nx * u[0][0] + ny);
-    ub[0][1] -= c * nx * nu;
+    ub[0][0] += c[0] * (nx * u[0][0] + ny);
+    ub[0][1] -= c[0] * nx * nu;
   }
 };
 
-// steady incompressible Navier-Stokes, outputs (u, v, p), coef = Re
+// steady incompressible Navier-Stokes, outputs (u, v, p), coef = Re; the
+// conservative fluxes of Table 1 (x-momentum, y-momentum, mass) dotted with n:
+//   (u^2 + p - u_x/Re, uv - u_y/Re), (uv - v_x/Re, v^2 + p - v_y/Re), (u, v)
 template <> struct Op<PDE_NS> {
   static constexpr int DO = 3, NEQ = 3;
   static constexpr bool S2 = true;
@@ -216,8 +218,27 @@ template <> struct Op<PDE_NS> {
     ub[2][1] += c[0];
     ub[2][2] += c[1];
   }
-  __device__ static float flux(const float (&u)[DO][4], float nx, float ny, float coef) { return 0.f; }
-  __device__ static void flux_adj(const float (&u)[DO][4], float, float, float, float, float (&)[DO][4]) {}
+  __device__ static void flux(const float (&u)[DO][4], float nx, float ny, float re, float (&fl)[NEQ]) {
+    const float ir = 1.f / re;
+    const float U = u[0][0], V = u[1][0], P = u[2][0];
+    // the viscous parts are -(n . grad u)/Re and -(n . grad v)/Re
+    const float un = fmaf(nx, u[0][1], ny * u[0][2]), vn = fmaf(nx, u[1][1], ny * u[1][2]);
+    fl[0] = fmaf(nx, fmaf(U, U, P), fmaf(ny, U * V, -ir * un));
+    fl[1] = fmaf(nx, U * V, fmaf(ny, fmaf(V, V, P), -ir * vn));
+    fl[2] = fmaf(nx, U, ny * V);
+  }
+  __device__ static void flux_adj(const float (&u)[DO][4], float nx, float ny, float re, const float (&c)[NEQ],
+                                  float (&ub)[DO][4]) {
+    const float ir = 1.f / re;
+    const float U = u[0][0], V = u[1][0];
+    ub[0][0] += c[0] * (2.f * nx * U + ny * V) + c[1] * nx * V + c[2] * nx;
+    ub[1][0] += c[0] * ny * U + c[1] * (nx * U + 2.f * ny * V) + c[2] * ny;
+    ub[2][0] += c[0] * nx + c[1] * ny;
+    ub[0][1] -= c[0] * ir * nx;
+    ub[0][2] -= c[0] * ir * ny;
+    ub[1][1] -= c[1] * ir * nx;
+    ub[1][2] -= c[1] * ir * ny;
+  }
 };
 
 // inverse diffusion div(K grad u) = f: both networks carry the (x, y)
@@ -468,9 +489,10 @@ struct Tile {
 #pragma unroll
       for (int e = 0; e < NEQ; ++e) ov[DO + e] = F[e];
     } else {
-      ov[DO] = Op<PDE>::flux(u, nx, ny, coef);
+      float fl[NEQ];
+      Op<PDE>::flux(u, nx, ny, coef, fl);
 #pragma unroll
-      for (int e = 1; e < NEQ; ++e) ov[DO + e] = 0.f;
+      for (int e = 0; e < NEQ; ++e) ov[DO + e] = fl[e];
     }
   }
 
@@ -544,27 +566,24 @@ struct Tile {
     } else if constexpr (PDE != PDE_INV) {
       const IfaceDesc ifd = ka.ifaces[it.iface];
       float ov[DO + NEQ];
-      own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
+      own_values(ifd.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
 #pragma unroll
       for (int c = 0; c < DO; ++c) {
         const float d = ov[c] - nb[c];
         loss[2] += 0.25f * d * d;
         ub[c][0] += 0.5f * nd.loss_w[2] * d * inv_n;
       }
-      if (ka.method == METHOD_XPINN) {
-        float c[NEQ];
+      // the fourth term: residual continuity (XPINN) or flux matching (cPINN),
+      // each equation's squared jump summed
+      float c[NEQ];
 #pragma unroll
-        for (int e = 0; e < NEQ; ++e) {
-          const float d = ov[DO + e] - nb[DO + e];
-          loss[3] += d * d;
-          c[e] = 2.f * nd.loss_w[3] * d * inv_n;
-        }
-        Op<PDE>::residual_adj(u, c, ka.coef0, ub);
-      } else {
-        const float d = ov[DO] - nb[DO];
+      for (int e = 0; e < NEQ; ++e) {
+        const float d = ov[DO + e] - nb[DO + e];
         loss[3] += d * d;
-        Op<PDE>::flux_adj(u, ifd.nx, ifd.ny, ka.coef0, 2.f * nd.loss_w[3] * d * inv_n, ub);
+        c[e] = 2.f * nd.loss_w[3] * d * inv_n;
       }
+      if (ifd.method == METHOD_XPINN) Op<PDE>::residual_adj(u, c, ka.coef0, ub);
+      else Op<PDE>::flux_adj(u, ifd.nx, ifd.ny, ka.coef0, c, ub);
     }
   }
 
@@ -631,7 +650,7 @@ struct Tile {
     if constexpr (VMODE == VAL_OWN) {
       const IfaceDesc ifd = ka.ifaces[it.iface];
       float ov[DO + NEQ];
-      own_values(ka.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
+      own_values(ifd.method, u, ifd.nx, ifd.ny, ka.coef0, ov);
 #pragma unroll
       for (int v = 0; v < DO + NEQ; ++v) dst[tp * (DO + NEQ) + v] = ov[v];
     } else if constexpr (VMODE == VAL_STREAMS) {

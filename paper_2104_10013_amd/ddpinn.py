@@ -24,7 +24,8 @@ DDP_RESIDUAL, DDP_DATA, DDP_DATA_AUX = 0, 1, 2
 DDP_OPT_CHUNK_POINTS, DDP_OPT_BLOCKS_PER_CU, DDP_OPT_ITEMS_PER_SLOT = 0, 1, 2
 
 EXPORTED = [
-    "ddp_create", "ddp_add_subdomain", "ddp_set_points", "ddp_add_interface", "ddp_set_option",
+    "ddp_create", "ddp_add_subdomain", "ddp_set_points", "ddp_add_interface", "ddp_set_interface_method",
+    "ddp_set_option",
     "ddp_finalize", "ddp_param_count", "ddp_set_params", "ddp_get_params", "ddp_loss_and_grad",
     "ddp_step", "ddp_get_state", "ddp_set_state", "ddp_eval", "ddp_sync", "ddp_time_kernels",
     "ddp_plan_dump", "ddp_plan", "ddp_last_error", "ddp_destroy", "ddp_autotune",
@@ -58,6 +59,7 @@ def load_library(path=LIB_PATH):
         "ddp_add_subdomain": ([P, I, pI, pI, pF, F, pI], I),
         "ddp_set_points": ([P, I, I, I, P, P, I], I),
         "ddp_add_interface": ([P, I, I, I, P, pF, I, pI], I),
+        "ddp_set_interface_method": ([P, I, I], I),
         "ddp_set_option": ([P, I, I64], I),
         "ddp_finalize": ([P, P, I], I),
         "ddp_param_count": ([P, I, pI64], I),
@@ -138,7 +140,10 @@ class Problem:
             for e in prob.interfaces:
                 xy = _host_f32(e.xy)
                 nrm = (ctypes.c_float * 2)(*[float(v) for v in e.normal])
-                _check(L.ddp_add_interface(self._h, e.a, e.b, xy.shape[0], _ptr(xy), nrm, 0, None))
+                eid = ctypes.c_int()
+                _check(L.ddp_add_interface(self._h, e.a, e.b, xy.shape[0], _ptr(xy), nrm, 0, ctypes.byref(eid)))
+                if getattr(e, "method", None) is not None:
+                    _check(L.ddp_set_interface_method(self._h, eid.value, _METHOD[e.method]))
             if chunk_points is not None:
                 _check(L.ddp_set_option(self._h, DDP_OPT_CHUNK_POINTS, int(chunk_points)))
             if blocks_per_cu is not None:

@@ -64,6 +64,9 @@ class Interface:
     b: int
     xy: np.ndarray          # (N_e, 2) float32
     normal: np.ndarray      # (2,) float32 unit normal pointing from a to b
+    # interface condition of this interface ("cpinn" flux or "xpinn" residual
+    # continuity); None: the problem's method
+    method: str | None = None
 
 
 @dataclass
@@ -371,6 +374,11 @@ def burgers_exact(x, t, nu, n_nodes=120):
     return out
 
 
+def ns_cpinn_kovasznay(seed=0, scale=1.0, re=40.0):
+    """The C4 problem with cPINN interfaces (Table 1 fluxes)."""
+    return c4_xpinn_kovasznay(seed=seed, scale=scale, re=re, method=METHOD_CPINN)
+
+
 def burgers_space_time(method, nx, nt, seed=0, scale=1.0, n_res=80000, width=20, depth=5,
                        n_ic=256, n_bc=100, n_iface=20, lr=8e-4):
     """The viscous Burgers problem of Sec. 7.5 (Eq. BE1: x in [-1,1], t in
@@ -384,9 +392,14 @@ def burgers_space_time(method, nx, nt, seed=0, scale=1.0, n_res=80000, width=20,
     points of each end line x = -1, +1 evenly over the time slabs.  Table 3
     pairs cPINN with nt = 1 and XPINN with nt > 1; the flux of the cPINN
     form is the space-time flux (u^2/2 - nu u_x, u), so a cPINN time
-    interface is defined as well.  Inputs are (x, t)."""
+    interface is defined as well.  method="hybrid" is the combination the
+    conclusions propose: cPINN flux matching across space interfaces, XPINN
+    residual continuity across time interfaces.  Inputs are (x, t)."""
     if nx < 1 or nt < 1:
         raise ValueError("nx and nt must be positive")
+    if method not in (METHOD_CPINN, METHOD_XPINN, "hybrid"):
+        raise ValueError(f"unknown method {method}")
+    hybrid = method == "hybrid"
     g, p, w, _ = _streams(seed)
     nu = 0.01 / math.pi
     xs = np.linspace(-1.0, 1.0, nx + 1)
@@ -420,10 +433,12 @@ def burgers_space_time(method, nx, nt, seed=0, scale=1.0, n_res=80000, width=20,
             q = it * nx + ix
             if ix + 1 < nx:   # space interface x = xs[ix+1], open in t
                 pts = _segment_points(p, n_i, (xs[ix + 1], ts[it]), (xs[ix + 1], ts[it + 1]))
-                ifaces.append(Interface(q, q + 1, _f32(pts), _f32([1.0, 0.0])))
+                ifaces.append(Interface(q, q + 1, _f32(pts), _f32([1.0, 0.0]),
+                                        METHOD_CPINN if hybrid else None))
             if it + 1 < nt:   # time interface t = ts[it+1], open in x
                 pts = _segment_points(p, n_i, (xs[ix], ts[it + 1]), (xs[ix + 1], ts[it + 1]))
-                ifaces.append(Interface(q, q + nx, _f32(pts), _f32([0.0, 1.0])))
+                ifaces.append(Interface(q, q + nx, _f32(pts), _f32([0.0, 1.0]),
+                                        METHOD_XPINN if hybrid else None))
     gx = np.linspace(-1.0, 1.0, 256)
     gt = np.linspace(0.0, 1.0, 101)
     X, T = np.meshgrid(gx, gt, indexing="ij")
@@ -440,21 +455,24 @@ def burgers_space_time(method, nx, nt, seed=0, scale=1.0, n_res=80000, width=20,
             cnt[idx] += 1
     exact = burgers_exact(ex[:, 0], ex[:, 1], nu)[:, None]
     name = f"burgers_{method}_{nx}x{nt}"
-    return Problem(name=name, method=method, pde=PDE_BURGERS1D, coef=(nu,), subdomains=subs,
+    return Problem(name=name, method=METHOD_CPINN if hybrid else method, pde=PDE_BURGERS1D, coef=(nu,), subdomains=subs,
                    interfaces=ifaces, eval_xy=exy32, eval_owner=owner, eval_exact=exact,
                    meta={"nx": nx, "nt": nt})
 
 
-def c4_xpinn_kovasznay(seed=0, scale=1.0, re=40.0):
+def c4_xpinn_kovasznay(seed=0, scale=1.0, re=40.0, method=METHOD_XPINN):
     """XPINN, steady NS (Eq. NSEq) at Re = 40 with the Kovasznay closed form on
     [-0.5,1] x [-0.5,1.5], 3x3 subdomains, nets 2-60x5-3, 10k residual points
-    each, 100 exact (u,v,p) points per outer segment, 200 per interface."""
+    each, 100 exact (u,v,p) points per outer segment, 200 per interface.
+    method="cpinn" matches the momentum and mass fluxes of Table 1 across the
+    interfaces instead of the residuals."""
     g, p, w, _ = _streams(seed)
     n_res = max(1, int(round(10000 * scale)))
     n_b = max(1, int(round(100 * scale)))
     n_i = max(1, int(round(200 * scale)))
+    name = "c4_xpinn_kovasznay" if method == METHOD_XPINN else "ns_cpinn_kovasznay"
     return _box_grid_problem(
-        "c4_xpinn_kovasznay", METHOD_XPINN, PDE_NS2D, (re,), g, p, w,
+        name, method, PDE_NS2D, (re,), g, p, w,
         [-0.5, 0.0, 0.5, 1.0], [-0.5, 1.0 / 6.0, 5.0 / 6.0, 1.5],
         lambda r, q: [2] + [60] * 5 + [3], lambda r, q: n_res, n_b, n_i,
         lambda x, y: kovasznay_exact(x, y, re), lambda x, y: np.zeros((len(x), 3)),
@@ -627,8 +645,9 @@ def _table3_entry(method, nx, nt):
     return make
 
 
-for _m, _nx, _nt in TABLE3_PARTITIONS:
+for _m, _nx, _nt in TABLE3_PARTITIONS + (("hybrid", 4, 4),):
     WORKLOADS[f"burgers_st_{_m}_{_nx}x{_nt}"] = _table3_entry(_m, _nx, _nt)
+WORKLOADS["ns_cpinn_kovasznay"] = ns_cpinn_kovasznay
 
 
 def make_problem(name, seed=0, scale=1.0, **kw):

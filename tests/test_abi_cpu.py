@@ -43,7 +43,8 @@ def _item_cost(nets, q, kind, count):
 
 
 @pytest.mark.parametrize("name", ["c1_cpinn_poisson", "c2_xpinn_poisson", "c3_cpinn_burgers", "c4_xpinn_kovasznay",
-                                  "c5_xpinn_inverse_diffusion", "burgers_st_xpinn_4x4", "burgers_st_cpinn_32x1"])
+                                  "c5_xpinn_inverse_diffusion", "burgers_st_xpinn_4x4", "burgers_st_cpinn_32x1",
+                                  "burgers_st_hybrid_4x4", "ns_cpinn_kovasznay"])
 def test_plan_covers_every_point_once(name, tmp_path):
     prob = W.make_problem(name, seed=0, scale=0.05 if name.startswith("c5") else 0.3)
     d = _plan(prob, tmp_path, chunk_points=100)
@@ -57,6 +58,9 @@ def test_plan_covers_every_point_once(name, tmp_path):
         for b, c in zip(begin[kind == k], count[kind == k]):
             cover[b:b + c] += 1
         assert (cover == 1).all()
+    # each interface keeps its own condition (the problem's unless set)
+    want = [ddpinn._METHOD[e.method or prob.method] for e in prob.interfaces]
+    assert [e["method"] for e in d["ifaces"]] == want
     # interface points: once per side
     cover = np.zeros((d["n_if"], 2), int)
     for b, c, s in zip(begin[kind == 2], count[kind == 2], side[kind == 2]):
@@ -148,7 +152,12 @@ def test_input_validation_codes():
     nrm = (ct.c_float * 2)(1, 0)
     assert L.ddp_add_interface(h, 0, 5, 2, xy.ctypes.data_as(ct.c_void_p), nrm, 0, None) == ddpinn.DDP_EINVAL
     assert L.ddp_add_interface(h, 1, 1, 2, xy.ctypes.data_as(ct.c_void_p), nrm, 0, None) == ddpinn.DDP_EINVAL
-    assert L.ddp_add_interface(h, 0, 1, 2, xy.ctypes.data_as(ct.c_void_p), nrm, 0, None) == 0
+    eid = ct.c_int(-1)
+    assert L.ddp_add_interface(h, 0, 1, 2, xy.ctypes.data_as(ct.c_void_p), nrm, 0, ct.byref(eid)) == 0
+    assert eid.value == 0
+    assert L.ddp_set_interface_method(h, 1, ddpinn.DDP_CPINN) == ddpinn.DDP_EINVAL   # unknown interface
+    assert L.ddp_set_interface_method(h, 0, 2) == ddpinn.DDP_EINVAL                  # unknown method
+    assert L.ddp_set_interface_method(h, 0, ddpinn.DDP_CPINN) == 0
     assert L.ddp_set_option(h, 99, 1) == ddpinn.DDP_EINVAL
     # calls that need a finalized problem
     assert L.ddp_step(h, 1, None) == ddpinn.DDP_ESTATE
@@ -163,7 +172,8 @@ def test_create_rejects_bad_combinations():
     import ctypes as ct
     h = ct.c_void_p()
     c = (ct.c_double * 1)(40.0)
-    assert L.ddp_create(ct.byref(h), 0, 2, c, 1) == ddpinn.DDP_EINVAL   # cPINN + NS
+    assert L.ddp_create(ct.byref(h), 0, 2, c, 1) == 0                   # cPINN + NS (Table 1 fluxes)
+    assert L.ddp_destroy(h) == 0
     assert L.ddp_create(ct.byref(h), 1, 1, c, 0) == ddpinn.DDP_EINVAL   # Burgers without nu
     assert L.ddp_create(ct.byref(h), 3, 0, c, 0) == ddpinn.DDP_EINVAL
     neg = (ct.c_double * 1)(-1.0)
@@ -187,6 +197,11 @@ def test_create_rejects_bad_combinations():
     xy = np.array([[0.1, 0.2]], np.float32)
     v = np.ones(1, np.float32)
     assert L.ddp_set_points(h, 0, 2, 1, xy.ctypes.data_as(ct.c_void_p), v.ctypes.data_as(ct.c_void_p), 0) == 0
+    assert L.ddp_add_subdomain(h, 2, two, w2, lw, 1e-3, None) == 0
+    nrm = (ct.c_float * 2)(1, 0)
+    assert L.ddp_add_interface(h, 0, 1, 1, xy.ctypes.data_as(ct.c_void_p), nrm, 0, None) == 0
+    assert L.ddp_set_interface_method(h, 0, ddpinn.DDP_CPINN) == ddpinn.DDP_EINVAL   # no flux for the inverse problem
+    assert L.ddp_set_interface_method(h, 0, ddpinn.DDP_XPINN) == 0
     assert L.ddp_destroy(h) == 0
     assert L.ddp_create(ct.byref(h), 1, 0, c, 0) == 0
     assert L.ddp_add_subdomain(h, 1, one, w1, lw, 1e-3, None) == 0

@@ -438,3 +438,46 @@ def test_space_time_burgers_training_trajectory_loosely_follows_oracle():
     _, hist_ref = oracle.train(prob, [s.params for s in prob.subdomains], n)
     np.testing.assert_allclose(hist[:, :, 0], hist_ref[:, :, 0], rtol=1e-3)
     pb.close()
+
+
+@pytest.mark.parametrize("scale,seed", [(0.1, 71), (1.0, None)])
+def test_ns_cpinn_kovasznay(scale, seed):
+    """Navier-Stokes with cPINN interfaces: the momentum and mass fluxes of
+    Table 1 matched across the 12 interfaces of the 3 x 3 Kovasznay problem."""
+    prob = W.ns_cpinn_kovasznay(seed=0, scale=scale)
+    params = _params(prob, seed)
+    for fused in ((True, False) if scale < 1 else (True,)):
+        _say(f"ns cpinn scale {scale} perturbation {seed} fused {fused}")
+        pb, lt, g = run(prob, params, fused=fused)
+        wl, wg = compare(prob, params, lt, g)
+        _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+        pb.close()
+
+
+def test_ns_cpinn_ragged_mixed_widths():
+    """cPINN Navier-Stokes on 2 x 2 boxes of widths 17..96 with tile-ragged
+    point counts and 1..67 interface points."""
+    widths = [[2, 17, 17, 3], [2, 40, 40, 40, 3], [2, 64] * 1 + [64] * 3 + [3], [2, 96, 96, 3]]
+    prob = W.custom_box_problem("cpinn", "ns2d_steady", 2, 2, widths, [65, 130, 1, 77], n_bnd_seg=5,
+                                n_iface=67, seed=9, coef=(40.0,), domain=(-0.5, 1.0, -0.5, 1.5))
+    prob.interfaces[1].xy = prob.interfaces[1].xy[:1].copy()
+    params = _params(prob, 10)
+    _say("ns cpinn ragged mixed widths")
+    pb, lt, g = run(prob, params, chunk_points=64)
+    compare(prob, params, lt, g)
+    pb.close()
+
+
+@pytest.mark.parametrize("seed", [None, 81])
+def test_space_time_burgers_hybrid(seed):
+    """cPINN flux matching across the space interfaces and XPINN residual
+    continuity across the time interfaces of the 4 x 4 space-time Burgers
+    decomposition, in one launch."""
+    prob = W.make_problem("burgers_st_hybrid_4x4", seed=0)
+    assert {e.method for e in prob.interfaces} == {"cpinn", "xpinn"}
+    params = _params(prob, seed)
+    _say(f"burgers hybrid 4x4 perturbation {seed}")
+    pb, lt, g = run(prob, params)
+    wl, wg = compare(prob, params, lt, g)
+    _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+    pb.close()

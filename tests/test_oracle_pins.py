@@ -556,3 +556,83 @@ def test_xpinn_time_interface_residual_continuity_by_fd():
     assert ref > 0
     for q in range(2):
         assert terms[q, 4] == pytest.approx(ref, rel=1e-5)
+
+
+# --------------------------------------------------------------------------
+# conservative fluxes (Table 1 for Navier-Stokes) and per-interface conditions
+
+
+@pytest.mark.parametrize("pde,widths,coef", [("poisson2d", [2, 5, 5, 1], ()), ("burgers1d", [2, 5, 5, 1], (0.01 / math.pi,)),
+                                             ("ns2d_steady", [2, 6, 5, 3], (40.0,))])
+def test_flux_divergence_is_the_residual(pde, widths, coef):
+    """div f(u) by central differences of the oracle's normal fluxes along
+    n = e_x and n = e_y equals the operator: -Lap u (Poisson), u_t + u u_x -
+    nu u_xx (Burgers, inputs (x, t)); for Navier-Stokes the divergence of the
+    momentum fluxes of Table 1 is F_1 + u F_3 and F_2 + v F_3, that of the
+    mass flux F_3 (f = 0)."""
+    rng = np.random.default_rng(8)
+    theta = _rand_theta(rng, widths)
+    z = torch.tensor(rng.uniform(-0.8, 0.8, (9, 2)), dtype=DT)
+    ex, ey = torch.tensor([1.0, 0.0], dtype=DT), torch.tensor([0.0, 1.0], dtype=DT)
+
+    def flux(zz, n):
+        return O.normal_flux(pde, coef, O.input_streams(theta, widths, zz, pde, create_graph=False), n)
+
+    h = 1e-5
+    div = ((flux(z + h * ex, ex) - flux(z - h * ex, ex)) + (flux(z + h * ey, ey) - flux(z - h * ey, ey))) / (2 * h)
+    st = O.input_streams(theta, widths, z, pde, create_graph=False)
+    F = O.residual(pde, coef, st, torch.zeros((z.shape[0], 3 if pde == "ns2d_steady" else 1), dtype=DT))
+    if pde == "ns2d_steady":
+        u, v = st["u"][:, 0], st["u"][:, 1]
+        F = torch.stack([F[:, 0] + u * F[:, 2], F[:, 1] + v * F[:, 2], F[:, 2]], 1)
+    np.testing.assert_allclose(div.numpy(), F.numpy(), rtol=1e-6, atol=1e-7 * float(F.abs().max()))
+
+
+def test_ns_cpinn_flux_term_and_gradient():
+    """Two Navier-Stokes boxes with cPINN interfaces: the flux term is the
+    mean over the interface of the summed squared jumps of the three normal
+    fluxes, written out from Table 1 here, and the gradient matches central
+    differences."""
+    prob = W.custom_box_problem("cpinn", "ns2d_steady", 2, 1, [[2, 4, 3, 3], [2, 3, 4, 3]], [7, 6],
+                                n_bnd_seg=3, n_iface=6, seed=6, coef=(40.0,), domain=(-0.5, 1.0, -0.5, 1.5))
+    params = [W.perturb_params(s.params, 4, 0.3) for s in prob.subdomains]
+    (e,) = prob.interfaces
+    nx, ny = (float(c) for c in e.normal)
+    z = torch.tensor(e.xy, dtype=DT)
+
+    def table1(q):
+        st = O.input_streams(torch.tensor(params[q], dtype=DT), prob.subdomains[q].widths, z, "ns2d_steady",
+                             create_graph=False)
+        (U, V, P), d = st["u"].T, st["du"]
+        re = 40.0
+        fxx, fxy = U * U + P - d[:, 0, 0] / re, U * V - d[:, 0, 1] / re
+        fyx, fyy = U * V - d[:, 1, 0] / re, V * V + P - d[:, 1, 1] / re
+        return torch.stack([nx * fxx + ny * fxy, nx * fyx + ny * fyy, nx * U + ny * V], 1)
+
+    ref = float(((table1(0) - table1(1)) ** 2).sum(1).mean())
+    terms, grads = O.loss_and_grad(prob, params)
+    assert terms[0, 4] == pytest.approx(ref, rel=1e-12) and terms[1, 4] == pytest.approx(ref, rel=1e-12)
+    for q in range(2):
+        np.testing.assert_allclose(grads[q], _fd_grad(prob, params, q), rtol=2e-6, atol=1e-8)
+
+
+def test_hybrid_interfaces_take_each_condition():
+    """cPINN across space interfaces, XPINN across time interfaces (2 x 2
+    space-time boxes): each subdomain's fourth term is the cPINN flux term of
+    its space interface plus the XPINN residual term of its time interface,
+    and the gradient matches central differences."""
+    hyb = _tiny_space_time("hybrid", 2, 2)
+    params = [W.perturb_params(s.params, 7, 0.3) for s in hyb.subdomains]
+    kinds = {(e.a, e.b): e.method for e in hyb.interfaces}
+    assert kinds == {(0, 1): "cpinn", (0, 2): "xpinn", (1, 3): "xpinn", (2, 3): "cpinn"}
+    terms, grads = O.loss_and_grad(hyb, params)
+    parts = {}
+    for method in ("cpinn", "xpinn"):
+        one = _tiny_space_time(method, 2, 2)
+        keep = "cpinn" if method == "cpinn" else "xpinn"
+        one.interfaces = [e for e, h in zip(one.interfaces, hyb.interfaces) if h.method == keep]
+        parts[method], _ = O.loss_and_grad(one, params)
+    np.testing.assert_allclose(terms[:, 4], parts["cpinn"][:, 4] + parts["xpinn"][:, 4], rtol=1e-12)
+    np.testing.assert_allclose(terms[:, 3], parts["cpinn"][:, 3] + parts["xpinn"][:, 3], rtol=1e-12)
+    for q in (0, 3):
+        np.testing.assert_allclose(grads[q], _fd_grad(hyb, params, q), rtol=2e-6, atol=1e-8)
