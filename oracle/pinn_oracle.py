@@ -6,8 +6,10 @@ only the tests, the smoke check and the CPU-baseline leg of the benchmark do.
 It computes, from the plain definitions and in float64 (inputs and parameters
 are the float32 values the GPU sees, converted exactly):
 
-* the network of Sec. 3: N^1 = W^1 z + b^1, N^k = W^k tanh(N^{k-1}) + b^k,
-  identity output layer (the adaptive slope n*a^k is fixed at 1);
+* the network of Sec. 3: N^1 = W^1 z + b^1, N^k = W^k Phi(n a^{k-1} N^{k-1}) + b^k,
+  identity output layer; Phi is tanh, sin or cos (chosen per subdomain, Table
+  4), and the layer-wise slopes a^k are trainable parameters when the network
+  is adaptive (else n a^k = 1);
 * input derivatives of the network output by automatic differentiation, as the
   paper does for the PDE residual (Sec. 4.1);
 * the residual F = L_x(u) - f of Eq. ProSet for the Poisson, Burgers (Eq. BE)
@@ -46,8 +48,18 @@ DIFF_INV = "diffusion2d_inv"
 # network (Sec. 3)
 
 
-def unpack(theta, widths):
-    """Split a flat parameter vector into [(W^k, b^k)], W^k of shape (N_k, N_{k-1})."""
+ACTIVATIONS = {"tanh": torch.tanh, "sin": torch.sin, "cos": torch.cos}
+
+
+def n_slopes(widths, slope_n):
+    """Trainable slopes of a network: one per hidden layer when adaptive."""
+    return len(widths) - 2 if slope_n is not None else 0
+
+
+def unpack(theta, widths, slope_n=None):
+    """Split a flat parameter vector into [(W^k, b^k)], W^k of shape
+    (N_k, N_{k-1}), and the slopes a^1..a^{L-1} that follow the layers of an
+    adaptive network (None otherwise)."""
     out, off = [], 0
     for k in range(1, len(widths)):
         nin, nout = widths[k - 1], widths[k]
@@ -56,18 +68,36 @@ def unpack(theta, widths):
         b = theta[off:off + nout]
         off += nout
         out.append((W, b))
+    ns = n_slopes(widths, slope_n)
+    slopes = theta[off:off + ns] if ns else None
+    off += ns
     assert off == theta.shape[0], (off, theta.shape)
-    return out
+    return out, slopes
 
 
-def mlp(theta, widths, z):
-    """N^L(z; Theta): tanh on hidden layers, identity on the last one."""
-    layers = unpack(theta, widths)
+def mlp(theta, widths, z, act="tanh", slope_n=None):
+    """N^L(z; Theta): Phi(n a^k x) on hidden layer k (n a^k = 1 unless the
+    network is adaptive, slope_n = n), identity on the last layer."""
+    layers, slopes = unpack(theta, widths, slope_n)
+    phi = ACTIVATIONS[act]
     h = z
     for k, (W, b) in enumerate(layers):
         a = h @ W.T + b
-        h = torch.tanh(a) if k < len(layers) - 1 else a
+        if k < len(layers) - 1:
+            if slopes is not None:
+                a = (slope_n * slopes[k]) * a
+            h = phi(a)
+        else:
+            h = a
     return h
+
+
+def net_kw(sd, which="u"):
+    """Activation keywords of a subdomain's network ("u", or "K" for the
+    conductivity network of the inverse problem, which shares the choice)."""
+    act = getattr(sd, "act", "tanh")
+    n = getattr(sd, "slope_n", 10.0) if getattr(sd, "adaptive", False) else None
+    return {"act": act, "slope_n": n}
 
 
 def second_order_set(pde):
@@ -77,11 +107,11 @@ def second_order_set(pde):
     return (0, 1)            # Laplacian in (x, y)
 
 
-def input_streams(theta, widths, z, pde, create_graph=True):
+def input_streams(theta, widths, z, pde, create_graph=True, act="tanh", slope_n=None):
     """u, grad u and the second-order sum  sum_{i in S} d^2 u / dz_i^2  per
     output component, by reverse-mode automatic differentiation w.r.t. z."""
     z = z.detach().clone().requires_grad_(True)
-    u = mlp(theta, widths, z)                      # (N, D_o)
+    u = mlp(theta, widths, z, act, slope_n)        # (N, D_o)
     n_out = u.shape[1]
     grads, lap = [], []
     S = second_order_set(pde)
@@ -142,6 +172,7 @@ def split_theta(prob, q, theta):
     if sd.aux_widths is None:
         return theta, None
     n = sum(sd.widths[k] * sd.widths[k - 1] + sd.widths[k] for k in range(1, len(sd.widths)))
+    n += n_slopes(sd.widths, net_kw(sd)["slope_n"])
     return theta[:n], theta[n:]
 
 
@@ -206,11 +237,11 @@ def interface_value(prob, q, theta, e, create_graph):
         if method != "xpinn":
             raise NotImplementedError("the inverse problem uses XPINN interfaces")
         thu, thk = split_theta(prob, q, theta)
-        stu = input_streams(thu, sd.widths, z, prob.pde, create_graph=create_graph)
-        stk = input_streams(thk, sd.aux_widths, z, prob.pde, create_graph=create_graph)
+        stu = input_streams(thu, sd.widths, z, prob.pde, create_graph=create_graph, **net_kw(sd))
+        stk = input_streams(thk, sd.aux_widths, z, prob.pde, create_graph=create_graph, **net_kw(sd, "K"))
         f0 = torch.zeros((z.shape[0], 1), dtype=DT)
         return torch.cat([stu["u"], stk["u"]], 1), residual_inverse(stu, stk, f0)
-    st = input_streams(theta, sd.widths, z, prob.pde, create_graph=create_graph)
+    st = input_streams(theta, sd.widths, z, prob.pde, create_graph=create_graph, **net_kw(sd))
     u = st["u"]
     if method == "cpinn":
         other = normal_flux(prob.pde, prob.coef, st, _t(e.normal))
@@ -235,20 +266,20 @@ def subdomain_terms(prob, q, thetas, grad_mode="local"):
     # data / boundary term (for the inverse problem also the K data; the two
     # mean squares are summed like the components of a vector solution)
     if sd.bnd_xy.shape[0] > 0:
-        ub = mlp(thu, sd.widths, _t(sd.bnd_xy))
+        ub = mlp(thu, sd.widths, _t(sd.bnd_xy), **net_kw(sd))
         mse_u = _mean_sq(ub - _t(sd.bnd_g))
     else:
         mse_u = torch.zeros((), dtype=DT)
     if thk is not None and sd.aux_xy.shape[0] > 0:
-        kb = mlp(thk, sd.aux_widths, _t(sd.aux_xy))
+        kb = mlp(thk, sd.aux_widths, _t(sd.aux_xy), **net_kw(sd, "K"))
         mse_u = mse_u + _mean_sq(kb - _t(sd.aux_g))
     # residual term
     if sd.res_xy.shape[0] > 0:
-        st = input_streams(thu, sd.widths, _t(sd.res_xy), prob.pde)
+        st = input_streams(thu, sd.widths, _t(sd.res_xy), prob.pde, **net_kw(sd))
         if thk is None:
             F = residual(prob.pde, prob.coef, st, _t(sd.res_f))
         else:
-            stk = input_streams(thk, sd.aux_widths, _t(sd.res_xy), prob.pde)
+            stk = input_streams(thk, sd.aux_widths, _t(sd.res_xy), prob.pde, **net_kw(sd, "K"))
             F = residual_inverse(st, stk, _t(sd.res_f))
         mse_f = _mean_sq(F)
     else:
@@ -347,9 +378,9 @@ def eval_stitched(prob, params, xy, owner):
                 continue
             sd = prob.subdomains[q]
             thu, thk = split_theta(prob, q, _t(params[q]))
-            u = mlp(thu, sd.widths, _t(xy[sel])).numpy()
+            u = mlp(thu, sd.widths, _t(xy[sel]), **net_kw(sd)).numpy()
             if inv:   # inverse problem: columns (u, K)
-                u = np.concatenate([u, mlp(thk, sd.aux_widths, _t(xy[sel])).numpy()], 1)
+                u = np.concatenate([u, mlp(thk, sd.aux_widths, _t(xy[sel]), **net_kw(sd, "K")).numpy()], 1)
             out[sel] += u / cnt[sel][:, None]
     return out
 

@@ -55,6 +55,13 @@ class Subdomain:
     aux_widths: list | None = None
     aux_xy: np.ndarray | None = None     # (N_K, 2) points with known K values
     aux_g: np.ndarray | None = None      # (N_K, 1) K targets
+    # activation of the subdomain's networks (Sec. 3, Table 4): Phi in
+    # {"tanh", "sin", "cos"} applied to n a^k x on hidden layer k; adaptive
+    # networks train the slopes a^k (one per hidden layer, stored after the
+    # layers of each network, initialised to n a^k = 1), else n a^k = 1
+    act: str = "tanh"
+    adaptive: bool = False
+    slope_n: float = 10.0
 
 
 @dataclass
@@ -102,18 +109,24 @@ class Problem:
 # parameters
 
 
-def param_count(widths):
-    return int(sum(widths[k] * widths[k - 1] + widths[k] for k in range(1, len(widths))))
+def param_count(widths, adaptive=False):
+    """Parameters of one network: per layer W and b, then one slope per
+    hidden layer when adaptive."""
+    n = sum(widths[k] * widths[k - 1] + widths[k] for k in range(1, len(widths)))
+    return int(n + (len(widths) - 2 if adaptive else 0))
 
 
-def glorot_params(rng, widths):
-    """Glorot-normal weights, zero biases, flat canonical layout."""
+def glorot_params(rng, widths, adaptive=False, slope_n=10.0):
+    """Glorot-normal weights, zero biases, flat canonical layout; an adaptive
+    network's slopes start at a^k = 1/n (n a^k = 1, Sec. 3)."""
     out = []
     for k in range(1, len(widths)):
         fan_in, fan_out = widths[k - 1], widths[k]
         std = math.sqrt(2.0 / (fan_in + fan_out))
         out.append(rng.normal(0.0, std, size=(fan_out, fan_in)).ravel())
         out.append(np.zeros(fan_out))
+    if adaptive:
+        out.append(np.full(len(widths) - 2, 1.0 / slope_n))
     return np.concatenate(out).astype(np.float32)
 
 
@@ -497,7 +510,12 @@ def _nearest(xy, sites):
     return np.argmin(d2, 1), d2
 
 
-def c5_xpinn_inverse_diffusion(seed=0, scale=1.0, n_cells=10):
+#: per-subdomain activations and residual counts of Table 4 (10 subdomains)
+TABLE4_ACTS = ("tanh", "sin", "cos", "tanh", "sin", "cos", "tanh", "sin", "cos", "tanh")
+TABLE4_NRES = (3000, 4000, 5000, 4000, 3000, 4000, 800, 3000, 5000, 4000)
+
+
+def c5_xpinn_inverse_diffusion(seed=0, scale=1.0, n_cells=10, table4=False):
     """XPINN for the inverse steady diffusion problem div(K grad u) = f
     (Eq. heq, Sec. 7.6): the conductivity K is a second network per subdomain,
     known only on the outer boundary, while u is observed inside the domain.
@@ -510,7 +528,13 @@ def c5_xpinn_inverse_diffusion(seed=0, scale=1.0, n_cells=10):
     points.  200 points on each shared Voronoi edge; 500 interior
     observations u + 1% noise; 400 outer-boundary points with u and K targets.
     Fields: u = sin(pi x) sin(pi y), K = 1 + 0.5 sin(2 pi x) cos(2 pi y).
-    Subdomain.params holds [u-net | K-net] (canonical layout each)."""
+    Subdomain.params holds [u-net | K-net] (canonical layout each).
+
+    table4=True takes the network set-up of Table 4 instead: 3 hidden layers
+    of 80 for both networks, the table's residual counts and per-subdomain
+    activation (tanh, sin, cos in turn) with trainable slopes (n = 10)."""
+    if table4 and n_cells != len(TABLE4_ACTS):
+        raise ValueError("Table 4 lists 10 subdomains")
     g, p, w, nz = _streams(seed)
     center = np.array([0.5, 0.5])
     amp = g.uniform(-0.06, 0.06, 4)
@@ -536,6 +560,9 @@ def c5_xpinn_inverse_diffusion(seed=0, scale=1.0, n_cells=10):
         uw.append([2] + [int(g.choice(wch))] * int(g.integers(3, 7)) + [1])
         kw.append([2] + [int(g.choice(wch))] * int(g.integers(3, 7)) + [1])
         nres.append(max(1, int(round(int(g.integers(1000, 30001)) * scale))))
+    if table4:
+        uw = kw = [[2, 80, 80, 80, 1]] * n_cells
+        nres = [max(1, int(round(n * scale))) for n in TABLE4_NRES]
 
     # residual points: uniform in the star, kept by nearest site up to each quota
     res = [np.zeros((0, 2)) for _ in range(n_cells)]
@@ -599,11 +626,12 @@ def c5_xpinn_inverse_diffusion(seed=0, scale=1.0, n_cells=10):
         so, sb = own_obs == q, own_bd == q
         dxy = np.concatenate([obs[so], bd[sb]], 0)
         dg = np.concatenate([u_obs[so], u_bd[sb]], 0)[:, None]
-        pu, pk = glorot_params(w, uw[q]), glorot_params(w, kw[q])
-        subs.append(Subdomain(widths=uw[q], loss_w=(1.0, 1.0, 1.0, 1.0), lr=6e-3,
+        pu, pk = glorot_params(w, uw[q], table4), glorot_params(w, kw[q], table4)
+        subs.append(Subdomain(widths=list(uw[q]), loss_w=(1.0, 1.0, 1.0, 1.0), lr=6e-3,
                               res_xy=_f32(r), res_f=_f32(f[:, None]), bnd_xy=_f32(dxy), bnd_g=_f32(dg),
-                              params=np.concatenate([pu, pk]), aux_widths=kw[q],
-                              aux_xy=_f32(bd[sb]), aux_g=_f32(k_bd[sb][:, None])))
+                              params=np.concatenate([pu, pk]), aux_widths=list(kw[q]),
+                              aux_xy=_f32(bd[sb]), aux_g=_f32(k_bd[sb][:, None]),
+                              act=TABLE4_ACTS[q] if table4 else "tanh", adaptive=table4))
     # evaluation grid inside the star; owners = nearest site(s)
     gx = np.linspace(lo[0], hi[0], 201)
     X, Y = np.meshgrid(gx, np.linspace(lo[1], hi[1], 201), indexing="ij")
@@ -618,7 +646,8 @@ def c5_xpinn_inverse_diffusion(seed=0, scale=1.0, n_cells=10):
         qs = np.nonzero(tie[i])[0][:4]
         owner[i, :len(qs)] = qs
     ue, ke, _ = diffusion_fields(ex[:, 0], ex[:, 1])
-    return Problem(name="c5_xpinn_inverse_diffusion", method=METHOD_XPINN, pde=PDE_DIFFUSION2D_INV,
+    return Problem(name="c5_table4_adaptive" if table4 else "c5_xpinn_inverse_diffusion", method=METHOD_XPINN,
+                   pde=PDE_DIFFUSION2D_INV,
                    coef=(), subdomains=subs, interfaces=ifaces, eval_xy=exy, eval_owner=owner,
                    eval_exact=np.stack([ue, ke], 1),
                    meta={"sites": sites, "center": center, "amp": amp, "phase": phase})
@@ -650,6 +679,15 @@ for _m, _nx, _nt in TABLE3_PARTITIONS + (("hybrid", 4, 4),):
 WORKLOADS["ns_cpinn_kovasznay"] = ns_cpinn_kovasznay
 
 
+def c5_table4_adaptive(seed=0, scale=1.0):
+    """The inverse problem with the networks of Table 4 (adaptive tanh / sin /
+    cos per subdomain, 3 x 80)."""
+    return c5_xpinn_inverse_diffusion(seed=seed, scale=scale, table4=True)
+
+
+WORKLOADS["c5_table4_adaptive"] = c5_table4_adaptive
+
+
 def make_problem(name, seed=0, scale=1.0, **kw):
     return WORKLOADS[name](seed=seed, scale=scale, **kw)
 
@@ -675,3 +713,19 @@ def custom_box_problem(method, pde, nx, ny, widths_list, n_res_list, n_bnd_seg, 
     return _box_grid_problem("custom", method, pde, coef, g, p, w, xs, ys,
                              lambda r, q: list(widths_list[q]), lambda r, q: int(n_res_list[q]),
                              n_bnd_seg, n_iface, ex, fo, loss_w, lr, (21, 21))
+
+
+def with_activations(prob, acts, adaptive=True, slope_n=10.0):
+    """Give subdomain q the activation acts[q % len(acts)] and, if adaptive,
+    trainable slopes initialised to n a^k = 1 (appended after the layers of each
+    of its networks).  Modifies and returns prob."""
+    for q, sd in enumerate(prob.subdomains):
+        sd.act = acts[q % len(acts)]
+        if adaptive and not sd.adaptive:
+            nu = param_count(sd.widths)
+            parts = [sd.params[:nu], np.full(len(sd.widths) - 2, 1.0 / slope_n)]
+            if sd.aux_widths is not None:
+                parts += [sd.params[nu:], np.full(len(sd.aux_widths) - 2, 1.0 / slope_n)]
+            sd.params = np.concatenate(parts).astype(np.float32)
+            sd.adaptive, sd.slope_n = True, slope_n
+    return prob

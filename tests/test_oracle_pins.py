@@ -636,3 +636,136 @@ def test_hybrid_interfaces_take_each_condition():
     np.testing.assert_allclose(terms[:, 3], parts["cpinn"][:, 3] + parts["xpinn"][:, 3], rtol=1e-12)
     for q in (0, 3):
         np.testing.assert_allclose(grads[q], _fd_grad(hyb, params, q), rtol=2e-6, atol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# activation choice and trainable slopes (Sec. 3, Table 4)
+
+
+@pytest.mark.parametrize("act", ["tanh", "sin", "cos"])
+def test_adaptive_input_streams_vs_central_fd(act):
+    """u, grad u and Lap u of an adaptive network (slopes away from 1/n)
+    against central differences of the network itself."""
+    rng = np.random.default_rng(12)
+    widths = [2, 5, 4, 1]
+    theta = torch.cat([_rand_theta(rng, widths), torch.tensor([0.13, 0.07], dtype=DT)])
+    z = torch.tensor(rng.uniform(-0.7, 0.7, (6, 2)), dtype=DT)
+    st = O.input_streams(theta, widths, z, "poisson2d", create_graph=False, act=act, slope_n=10.0)
+    f = lambda zz: O.mlp(theta, widths, zz, act, 10.0)[:, 0]
+    h = 1e-4
+    e = [torch.tensor([h, 0.0], dtype=DT), torch.tensor([0.0, h], dtype=DT)]
+    for i in range(2):
+        d1 = (f(z + e[i]) - f(z - e[i])) / (2 * h)
+        np.testing.assert_allclose(st["du"][:, 0, i].numpy(), d1.numpy(), rtol=1e-6, atol=1e-8)
+    lap = sum((f(z + e[i]) - 2 * f(z) + f(z - e[i])) / h ** 2 for i in range(2))
+    np.testing.assert_allclose(st["lap"][:, 0].numpy(), lap.numpy(), rtol=1e-4, atol=1e-5)
+
+
+def test_activation_closed_forms():
+    """One hidden neuron: u = w2 Phi(n a (w1 . z + b1)) + b2 for each Phi."""
+    z = torch.tensor([[0.3, -0.2]], dtype=DT)
+    w1, b1, w2, b2, a = [0.7, -1.1], 0.25, 1.3, -0.4, 0.15
+    theta = torch.tensor(w1 + [b1, w2, b2, a], dtype=DT)
+    y = 10.0 * a * (0.7 * 0.3 - 1.1 * -0.2 + 0.25)
+    for act, fn in (("tanh", math.tanh), ("sin", math.sin), ("cos", math.cos)):
+        u = float(O.mlp(theta, [2, 1, 1], z, act, 10.0)[0, 0])
+        assert u == pytest.approx(w2 * fn(y) + b2, rel=1e-14)
+    # not adaptive: n a^k = 1
+    assert float(O.mlp(theta[:-1], [2, 1, 1], z, "sin")[0, 0]) == pytest.approx(w2 * math.sin(y / (10 * a)) + b2,
+                                                                                  rel=1e-14)
+
+
+def _adaptive_two_box(method, acts, pde="poisson2d", seed=3):
+    if pde == "poisson2d":
+        prob = W.custom_box_problem(method, pde, 2, 1, [[2, 4, 3, 1], [2, 3, 3, 3, 1]], [9, 8], n_bnd_seg=4,
+                                    n_iface=6, seed=seed)
+    else:
+        prob = W.custom_box_problem(method, pde, 2, 1, [[2, 4, 3, 3], [2, 3, 4, 3]], [7, 6], n_bnd_seg=3,
+                                    n_iface=5, seed=seed, coef=(40.0,), domain=(-0.5, 1.0, -0.5, 1.5))
+    return W.with_activations(prob, acts)
+
+
+@pytest.mark.parametrize("method,acts", [("xpinn", ("sin", "cos")), ("cpinn", ("cos", "tanh")),
+                                         ("xpinn", ("tanh", "sin"))])
+def test_adaptive_gradient_vs_central_fd(method, acts):
+    """Gradients of weights, biases and slopes of adaptive networks with
+    different activations on the two sides of an interface."""
+    prob = _adaptive_two_box(method, acts)
+    params = [W.perturb_params(s.params, 5, 0.3) for s in prob.subdomains]
+    _, grads = O.loss_and_grad(prob, params)
+    for q in range(2):
+        assert grads[q].shape == (W.param_count(prob.subdomains[q].widths, True),)
+        np.testing.assert_allclose(grads[q], _fd_grad(prob, params, q), rtol=2e-6, atol=1e-8)
+
+
+def _slope_identity(widths, theta, grad, n_nets_widths=None):
+    """a^k dJ/da^k - (<W^k, dJ/dW^k> + <b^k, dJ/db^k>) for every hidden layer
+    k of each network (zero: scaling n a^k by lambda equals scaling W^k, b^k)."""
+    out, off = [], 0
+    for wd in n_nets_widths or [widths]:
+        lay = []
+        for k in range(1, len(wd)):
+            n = wd[k] * wd[k - 1] + wd[k]
+            lay.append(slice(off, off + n))
+            off += n
+        for k in range(len(wd) - 2):
+            s = off + k
+            out.append((theta[s] * grad[s], float(np.dot(theta[lay[k]], grad[lay[k]]))))
+        off += len(wd) - 2
+    assert off == theta.size
+    return out
+
+
+@pytest.mark.parametrize("pde,acts", [("poisson2d", ("sin", "cos")), ("ns2d_steady", ("tanh", "cos"))])
+def test_slope_gradient_scaling_identity(pde, acts):
+    """a^k dJ/da^k = <W^k, dJ/dW^k> + <b^k, dJ/db^k>: the slope scales the
+    pre-activation of layer k exactly as a common factor on W^k and b^k."""
+    prob = _adaptive_two_box("xpinn", acts, pde=pde)
+    params = [W.perturb_params(s.params, 6, 0.3) for s in prob.subdomains]
+    _, grads = O.loss_and_grad(prob, params)
+    for q in range(2):
+        th = params[q].astype(np.float64)
+        for lhs, rhs in _slope_identity(prob.subdomains[q].widths, th, grads[q]):
+            assert lhs == pytest.approx(rhs, rel=1e-10, abs=1e-14)
+
+
+def test_adaptive_at_initial_slopes_equals_fixed_activation():
+    """With n a^k = 1 an adaptive network computes what the fixed network
+    computes: same loss terms and the same weight and bias gradients (n = 8
+    here, so that a^k = 1/n is exact in float32)."""
+    fixed = _two_box("xpinn")
+    adapt = W.with_activations(_two_box("xpinn"), ("tanh",), slope_n=8.0)
+    tf, gf = O.loss_and_grad(fixed, [s.params for s in fixed.subdomains])
+    ta, ga = O.loss_and_grad(adapt, [s.params for s in adapt.subdomains])
+    np.testing.assert_allclose(ta, tf, rtol=1e-13)
+    for q in range(2):
+        n = gf[q].size
+        np.testing.assert_allclose(ga[q][:n], gf[q], rtol=1e-12, atol=1e-15)
+        assert ga[q].size == n + len(fixed.subdomains[q].widths) - 2
+
+
+def test_table4_inverse_problem_inputs_and_gradient():
+    """The inverse problem with Table 4's networks: activations and residual
+    counts as listed; a small instance's gradient (both networks, slopes
+    included) against central differences on sampled entries and the slope
+    identity for every layer of both networks."""
+    full = W.c5_table4_adaptive(seed=0)
+    assert [s.act for s in full.subdomains] == list(W.TABLE4_ACTS)
+    assert [s.res_xy.shape[0] for s in full.subdomains] == list(W.TABLE4_NRES)
+    assert all(s.widths == [2, 80, 80, 80, 1] and s.aux_widths == [2, 80, 80, 80, 1] and s.adaptive
+               for s in full.subdomains)
+    prob = W.c5_table4_adaptive(seed=1, scale=0.004)
+    for s in prob.subdomains:
+        s.widths, s.aux_widths = [2, 4, 3, 1], [2, 3, 3, 1]
+        rng = np.random.default_rng(2)
+        s.params = np.concatenate([W.glorot_params(rng, s.widths, True), W.glorot_params(rng, s.aux_widths, True)])
+    params = [W.perturb_params(s.params, 8, 0.3) for s in prob.subdomains]
+    _, grads = O.loss_and_grad(prob, params)
+    for q in (0, 1, 2):
+        sd = prob.subdomains[q]
+        idx = list(range(0, params[q].size, 3)) + [params[q].size - 1]
+        # J is O(100) here: a wider step keeps the rounding of the differences small
+        fd = _fd_grad(prob, params, q, h=1e-5, idx=idx)
+        np.testing.assert_allclose(grads[q][idx], fd[idx], rtol=2e-6, atol=1e-7 * np.abs(grads[q]).max())
+        for lhs, rhs in _slope_identity(None, params[q].astype(np.float64), grads[q], [sd.widths, sd.aux_widths]):
+            assert lhs == pytest.approx(rhs, rel=1e-10, abs=1e-14)
