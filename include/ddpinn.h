@@ -70,6 +70,9 @@ enum { DDP_CPINN = 0, DDP_XPINN = 1 };
  *                 the pair (u, K) and the operator value L(u, K). */
 enum { DDP_POISSON2D = 0, DDP_BURGERS1D = 1, DDP_NS2D_STEADY = 2, DDP_DIFFUSION2D_INV = 3 };
 
+/* hidden-layer activations Phi (Sec. 3; per subdomain, Table 4) */
+enum { DDP_ACT_TANH = 0, DDP_ACT_SIN = 1, DDP_ACT_COS = 2 };
+
 /* point kinds for ddp_set_points; DATA_AUX = points with known K values
  * (inverse problem), whose squared misfit is added to MSE_u */
 enum { DDP_RESIDUAL = 0, DDP_DATA = 1, DDP_DATA_AUX = 2 };
@@ -113,6 +116,17 @@ int ddp_set_points(ddp_problem* p, int sd, int kind, int n, const float* xy, con
  * networks are evaluated at the same points.  *if_id receives its index. */
 int ddp_add_interface(ddp_problem* p, int sd_a, int sd_b, int n, const float* xy,
                       const float normal[2], int on_device, int* if_id);
+
+/* Activation of subdomain sd's networks (default: tanh, not adaptive).  Hidden
+ * layer k applies Phi(n a^k x) to its pre-activation x (Sec. 3), Phi = tanh,
+ * sin or cos (act = DDP_ACT_*).  adaptive = 1 makes the slopes a^1..a^D of
+ * each network trainable parameters with scale n = slope_n: they follow that
+ * network's layers in the canonical flat layout (so ddp_param_count grows by
+ * D per network), their gradients are dJ/da^k, Adam updates them, and the
+ * paper initialises them to n a^k = 1.  adaptive = 0 fixes n a^k = 1.
+ * DDP_EINVAL for an unknown subdomain or activation, adaptive not 0/1, or
+ * slope_n not finite and > 0.  Valid before ddp_finalize. */
+int ddp_set_activation(ddp_problem* p, int sd, int act, int adaptive, float slope_n);
 
 /* Give interface if_id its own condition, DDP_CPINN (flux matching) or
  * DDP_XPINN (residual continuity), instead of the problem's: e.g. cPINN

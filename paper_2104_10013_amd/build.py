@@ -12,23 +12,31 @@ ARCH = "gfx950"
 # packed FP32 VALU forms are disabled for every HIP object
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["kernels.hip", "ddpinn.cpp"]
+# (source, extra flags, object): the train kernels of each of the four
+# operators, plain and with the general activation rule, each in a
+# translation unit of their own, compiled in parallel
+UNITS = [("kernels.hip", [], "kernels.o")] + \
+        [("kernels.hip", ["-DDDP_TRAIN_PDE=%d" % pde], "kernels_pde%d.o" % pde) for pde in range(4)] + \
+        [("kernels.hip", ["-DDDP_TRAIN_PDE=%d" % pde, "-DDDP_TRAIN_GA"], "kernels_pde%d_ga.o" % pde)
+         for pde in range(4)] + \
+        [("ddpinn.cpp", [], "ddpinn.o")]
 
 
-def _compile(src, obj):
-    cmd = [HIPCC] + HIP_FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit, bdir):
+    src, extra, obj = unit
+    obj = os.path.join(bdir, obj)
+    cmd = [HIPCC] + HIP_FLAGS + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr))
+        raise RuntimeError("hipcc failed for %s %s:\n%s" % (src, " ".join(extra), r.stderr))
     return obj
 
 
 def build(verbose=True):
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = [os.path.join(bdir, s.rsplit(".", 1)[0] + ".o") for s in SOURCES]
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        list(ex.map(_compile, SOURCES, objs))
+    with ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+        objs = list(ex.map(lambda u: _compile(u, bdir), UNITS))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -16,6 +16,8 @@ constexpr int kLossTerms = 4;     // MSE_u, MSE_F, MSE_uavg, MSE_flux|MSE_R
 enum Kind { KIND_RES = 0, KIND_DATA = 1, KIND_IFACE = 2, KIND_AUX = 3 };
 enum Pde { PDE_POISSON = 0, PDE_BURGERS = 1, PDE_NS = 2, PDE_INV = 3 };
 enum Method { METHOD_CPINN = 0, METHOD_XPINN = 1 };
+// hidden-layer activation Phi (Sec. 3; chosen per subdomain in Table 4)
+enum Act { ACT_TANH = 0, ACT_SIN = 1, ACT_COS = 2 };
 
 // One network: widths 2 -> w (x depth) -> d_out.
 //
@@ -26,9 +28,12 @@ enum Method { METHOD_CPINN = 0, METHOD_XPINN = 1 };
 //   per hidden layer k = 2..D:
 //     [WP][WS]         W^k            [WP][WS]  W^k transposed    [WP]  b^k
 //   [d_out][WP]        output W^L     [4]       b^L
+//   [kMaxDepth]        effective slopes c_k = n a^k of hidden layers 1..D
+//                      (adaptive networks only; otherwise 1 is used)
 // Gradient partial rows use the same order without the transposes and
 // without the row padding:  [WP][4], per hidden layer [WP][WP] + [WP],
-// [d_out][WP] + [4].
+// [d_out][WP] + [4], [kMaxDepth] (dJ/dc_k).  Canonical parameters of an
+// adaptive network end with its D slopes a^1..a^D.
 //
 // A subdomain owns one network, or two for the inverse diffusion problem (the
 // solution u, then the conductivity K at the next index).  Networks are the
@@ -49,6 +54,9 @@ struct NetDesc {
   int gsize;        // floats of one gradient partial row
   float loss_w[4];  // W_u, W_F, W_I, W_flux | W_IF
   float lr;
+  int act;          // Act
+  int adaptive;     // 1: trainable slopes a^k (canonical parameters after the layers)
+  float slope_n;    // the scale n of the slopes (c_k = n a^k)
 };
 
 // kernel-layout and partial-row offsets (floats) of a network
@@ -61,12 +69,14 @@ struct Layout {
   __host__ __device__ int k_b(int k) const { return k_hidden(k) + 2 * WP * WS; }
   __host__ __device__ int k_out() const { return k_hidden(D + 1); }
   __host__ __device__ int k_bout() const { return k_out() + DO * WP; }
-  __host__ __device__ int k_size() const { return k_bout() + 4; }
+  __host__ __device__ int k_slope() const { return k_bout() + 4; }
+  __host__ __device__ int k_size() const { return k_slope() + kMaxDepth; }
   __host__ __device__ int g_w(int k) const { return 4 * WP + (k - 2) * (WP * WP + WP); }
   __host__ __device__ int g_b(int k) const { return g_w(k) + WP * WP; }
   __host__ __device__ int g_out() const { return g_w(D + 1); }
   __host__ __device__ int g_bout() const { return g_out() + DO * WP; }
-  __host__ __device__ int g_size() const { return g_bout() + 4; }
+  __host__ __device__ int g_slope() const { return g_bout() + 4; }
+  __host__ __device__ int g_size() const { return g_slope() + kMaxDepth; }
 };
 
 // One work item: a contiguous range of one point set evaluated by one network.

@@ -45,6 +45,9 @@ struct HostSd {
   float lr;
   std::vector<float> res_xy, res_f, dat_xy, dat_g, aux_xy, aux_g;
   int n_res = 0, n_dat = 0, n_aux = 0;
+  int act = DDP_ACT_TANH;   // activation of the subdomain's networks
+  int adaptive = 0;         // 1: trainable slopes, one per hidden layer of each network
+  float slope_n = 10.f;
 };
 
 struct HostIf {
@@ -83,7 +86,8 @@ struct ddp_problem {
   // plan
   bool planned = false, finalized = false;
   int fused = 1;
-  int wpmax = 16;
+  int wpmax = 16;                // width group of the (plain path's) train kernel
+  bool ga = false;               // some network needs the general activation rule
   std::vector<NetDesc> nets;     // a subdomain's networks are adjacent: u [, K]
   std::vector<int> sd_net;       // n_sd + 1: first network of each subdomain
   std::vector<int64_t> sd_poff;  // n_sd + 1: parameter offsets of subdomains
@@ -188,10 +192,10 @@ int copy_in(const float* src, size_t n, int on_device, std::vector<float>& dst) 
   return DDP_OK;
 }
 
-int64_t net_param_count(const std::vector<int>& wd) {
+int64_t net_param_count(const std::vector<int>& wd, int adaptive) {
   int64_t n = 0;
   for (size_t k = 1; k < wd.size(); ++k) n += (int64_t)wd[k] * wd[k - 1] + wd[k];
-  return n;
+  return n + (adaptive ? (int64_t)wd.size() - 2 : 0);
 }
 
 double item_cost(const NetDesc& nd, int count) {
@@ -223,6 +227,7 @@ int build_plan(ddp_problem* p) {
   p->net_poff.assign(1, 0);
   p->kparam_floats = 0;
   p->wpmax = 16;
+  p->ga = false;
   for (int q = 0; q < n_sd; ++q) {
     const HostSd& s = p->sds[q];
     p->sd_net[q] = (int)p->nets.size();
@@ -236,7 +241,7 @@ int build_plan(ddp_problem* p) {
       nd.d_out = wd.back();
       nd.wclass = width_class(nd.width);
       nd.poff = p->net_poff.back();
-      nd.n_params = (int)net_param_count(wd);
+      nd.n_params = (int)net_param_count(wd, s.adaptive);
       const Layout L(nd.wclass, nd.depth, nd.d_out);
       nd.koff = p->kparam_floats;
       nd.ksize = L.k_size();
@@ -244,13 +249,18 @@ int build_plan(ddp_problem* p) {
       p->kparam_floats += nd.ksize;
       for (int k = 0; k < 4; ++k) nd.loss_w[k] = s.loss_w[k];
       nd.lr = s.lr;
+      nd.act = s.act;
+      nd.adaptive = s.adaptive;
+      nd.slope_n = s.slope_n;
       p->net_poff.push_back(nd.poff + nd.n_params);
       p->wpmax = std::max(p->wpmax, nd.wclass);
+      if (nd.act != ACT_TANH || nd.adaptive) p->ga = true;
       p->nets.push_back(nd);
     }
     p->sd_poff[q + 1] = p->net_poff.back();
   }
   p->sd_net[n_sd] = (int)p->nets.size();
+  p->wpmax = kernel_wpmax(p->wpmax, p->ga);
 
   // packed point arrays
   p->h_res_xy.clear();
@@ -396,7 +406,7 @@ int build_plan(ddp_problem* p) {
     for (auto* grp : {&narrow, &wide}) {
       if (grp->empty()) continue;
       ddp_problem::Launch l;
-      l.wpmax = grp == &narrow ? w_narrow : w_wide;
+      l.wpmax = kernel_wpmax(grp == &narrow ? w_narrow : w_wide, p->ga);
       l.begin = (int)p->titems.size();
       l.count = (int)grp->size();
       p->titems.insert(p->titems.end(), grp->begin(), grp->end());
@@ -519,7 +529,7 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
       ka.scratch_slot = l.slot_floats;
       ka.prologue = g == 0;
       const int grid = std::max(1, std::min(l.n_slots, l.count));
-      HIP_TRY(launch_train(p->pde, l.wpmax, ka, grid, st));
+      HIP_TRY(launch_train(p->pde, l.wpmax, p->ga, ka, grid, st));
     }
     RArgs ra = make_rargs(p);
     reduce_range(p, ra, 0, n_sd);
@@ -541,7 +551,7 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     ka.prologue = q == 0;
     if (ka.n_items == 0 && q != 0) continue;
     const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
-    HIP_TRY(launch_train(p->pde, p->wpmax, ka, grid, st));
+    HIP_TRY(launch_train(p->pde, p->wpmax, p->ga, ka, grid, st));
   }
   for (int q = 0; q < n_sd; ++q) {
     RArgs ra = make_rargs(p);
@@ -712,6 +722,23 @@ int ddp_add_interface(ddp_problem* p, int sd_a, int sd_b, int n, const float* xy
   return DDP_OK;
 }
 
+static_assert(DDP_ACT_TANH == ACT_TANH && DDP_ACT_SIN == ACT_SIN && DDP_ACT_COS == ACT_COS,
+              "activation codes of the ABI and the kernels agree");
+
+int ddp_set_activation(ddp_problem* p, int sd, int act, int adaptive, float slope_n) {
+  if (int rc = check_open(p)) return rc;
+  if (sd < 0 || sd >= (int)p->sds.size()) return fail(DDP_EINVAL, "unknown subdomain");
+  if (act != DDP_ACT_TANH && act != DDP_ACT_SIN && act != DDP_ACT_COS) return fail(DDP_EINVAL, "unknown activation");
+  if (adaptive != 0 && adaptive != 1) return fail(DDP_EINVAL, "adaptive must be 0 or 1");
+  if (!std::isfinite(slope_n) || slope_n <= 0.f) return fail(DDP_EINVAL, "slope scale must be finite and > 0");
+  HostSd& s = p->sds[sd];
+  s.act = act;
+  s.adaptive = adaptive;
+  s.slope_n = slope_n;
+  p->planned = false;
+  return DDP_OK;
+}
+
 int ddp_set_interface_method(ddp_problem* p, int if_id, int method) {
   if (int rc = check_open(p)) return rc;
   if (if_id < 0 || if_id >= (int)p->ifs.size()) return fail(DDP_EINVAL, "unknown interface");
@@ -773,7 +800,7 @@ int install_plan(ddp_problem* p) {
   p->slot_floats = scratch_slot_floats(p->pde, p->wpmax);
   int64_t scratch_floats = (int64_t)p->n_slots * p->slot_floats;
   for (ddp_problem::Launch& l : p->launches) {
-    HIP_TRY(train_occupancy(p->pde, l.wpmax, &l.occupancy));
+    HIP_TRY(train_occupancy(p->pde, l.wpmax, p->ga, &l.occupancy));
     if (l.occupancy < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
     const int b = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, l.occupancy) : l.occupancy;
     l.n_slots = std::max(1, p->n_cu * b);
@@ -831,6 +858,8 @@ uint64_t problem_signature(const ddp_problem* p) {
   for (const HostSd& s : p->sds) {
     for (int w : s.widths) mix(w);
     for (int w : s.aux_widths) mix(w);
+    mix(s.act);
+    mix(s.adaptive);
     mix(s.n_res);
     mix(s.n_dat);
     mix(s.n_aux);
@@ -879,7 +908,7 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   HIP_TRY(hipGetDevice(&p->device));
   p->stream = static_cast<hipStream_t>(hip_stream);
   HIP_TRY(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
-  HIP_TRY(train_occupancy(p->pde, p->wpmax, &p->occupancy));
+  HIP_TRY(train_occupancy(p->pde, p->wpmax, p->ga, &p->occupancy));
   if (p->occupancy < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
 
   int rc = 0;
@@ -1001,7 +1030,7 @@ int ddp_param_count(const ddp_problem* p, int sd, int64_t* n) {
   if (!p || !n) return fail(DDP_EINVAL, "null argument");
   if (sd < 0 || sd >= (int)p->sds.size()) return fail(DDP_EINVAL, "unknown subdomain");
   const HostSd& s = p->sds[sd];
-  *n = net_param_count(s.widths) + (s.aux_widths.empty() ? 0 : net_param_count(s.aux_widths));
+  *n = net_param_count(s.widths, s.adaptive) + (s.aux_widths.empty() ? 0 : net_param_count(s.aux_widths, s.adaptive));
   return DDP_OK;
 }
 
@@ -1130,7 +1159,7 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
           }
           if (ka.n_items == 0) continue;
           const int grid = std::max(1, std::min(n_slots, ka.n_items));
-          HIP_TRY(launch_train(p->pde, wpmax, ka, grid, p->stream));
+          HIP_TRY(launch_train(p->pde, wpmax, p->ga, ka, grid, p->stream));
         }
       } else {
         RArgs ra = make_rargs(p);
@@ -1165,9 +1194,10 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
     const NetDesc& n = p->nets[q];
     std::fprintf(f,
                  "%s{\"sd\": %d, \"pair\": %d, \"width\": %d, \"depth\": %d, \"d_out\": %d, \"wclass\": %d, "
-                 "\"poff\": %lld, \"n_params\": %d, \"koff\": %lld, \"ksize\": %d, \"gsize\": %d}",
+                 "\"poff\": %lld, \"n_params\": %d, \"koff\": %lld, \"ksize\": %d, \"gsize\": %d, \"act\": %d, "
+                 "\"adaptive\": %d}",
                  q ? ", " : "", n.sd, n.pair, n.width, n.depth, n.d_out, n.wclass, (long long)n.poff, n.n_params,
-                 (long long)n.koff, n.ksize, n.gsize);
+                 (long long)n.koff, n.ksize, n.gsize, n.act, n.adaptive);
   }
   std::fprintf(f, "],\n\"ifaces\": [");
   for (size_t e = 0; e < p->ifaces.size(); ++e) {

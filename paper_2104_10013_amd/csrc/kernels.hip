@@ -142,6 +142,65 @@ __device__ __forceinline__ void tanh_adj(float a, float ax, float ay, float al, 
   ab = fmaf(s1, g, fmaf(s2, fmaf(ax, gx, ay * gy), fmaf(s2, al, s3 * q) * gl));
 }
 
+// General activation (Sec. 3): h = Phi(c a) with the effective slope c = n a^k
+// of the layer and Phi in {tanh, sin, cos}.  The Taylor streams of y = c a are
+// c times those of a, so the rule is the unit-slope one on the scaled streams:
+// h = Phi(y), d_i h = Phi'(y) d_i y, Delta_S h = Phi'(y) Delta_S y +
+// Phi''(y) sum_{i in S} (d_i y)^2.
+__device__ __forceinline__ void act_derivs(int act, float y, float& f0, float& f1, float& f2, float& f3) {
+  if (act == ACT_TANH) {
+    float t, s1;
+    tanh_s1(y, t, s1);
+    f0 = t;
+    f1 = s1;
+    f2 = -2.f * t * s1;
+    f3 = -2.f * s1 * (1.f - 3.f * t * t);
+  } else {
+    float sn, cs;
+    sincosf(y, &sn, &cs);
+    f0 = act == ACT_SIN ? sn : cs;
+    f1 = act == ACT_SIN ? cs : -sn;
+    f2 = -f0;
+    f3 = -f1;
+  }
+}
+
+template <bool S2>
+__device__ __forceinline__ void act_rule(int act, float c, float a, float ax, float ay, float al, float& h,
+                                         float& hx, float& hy, float& hl) {
+  const float y = c * a, yx = c * ax, yy = c * ay, yl = c * al;
+  float f0, f1, f2, f3;
+  act_derivs(act, y, f0, f1, f2, f3);
+  h = f0;
+  hx = f1 * yx;
+  hy = f1 * yy;
+  const float q = S2 ? fmaf(yx, yx, yy * yy) : yx * yx;
+  hl = fmaf(f1, yl, f2 * q);
+}
+
+// Adjoint of act_rule: from the adjoints g of (h, d_i h, Delta_S h) the
+// adjoints of the unscaled streams a (c times those of the scaled streams y),
+// and dc += the derivative of the layer's share of J with respect to c, i.e.
+// the adjoints of y dotted with the streams of a.
+template <bool S2>
+__device__ __forceinline__ void act_adj(int act, float c, float a, float ax, float ay, float al, float g, float gx,
+                                        float gy, float gl, float& ab, float& abx, float& aby, float& abl,
+                                        float& dc) {
+  const float y = c * a, yx = c * ax, yy = c * ay, yl = c * al;
+  float f0, f1, f2, f3;
+  act_derivs(act, y, f0, f1, f2, f3);
+  const float q = S2 ? fmaf(yx, yx, yy * yy) : yx * yx;
+  const float bl = f1 * gl;
+  const float bx = fmaf(f1, gx, 2.f * f2 * yx * gl);
+  const float by = S2 ? fmaf(f1, gy, 2.f * f2 * yy * gl) : f1 * gy;
+  const float b = fmaf(f1, g, fmaf(f2, fmaf(yx, gx, yy * gy), fmaf(f2, yl, f3 * q) * gl));
+  dc = fmaf(b, a, fmaf(bx, ax, fmaf(by, ay, fmaf(bl, al, dc))));
+  ab = c * b;
+  abx = c * bx;
+  aby = c * by;
+  abl = c * bl;
+}
+
 // ---------------------------------------------------------------------------
 // Operators.  u[c][s]: output c, stream s = (value, d/dz0, d/dz1, second order).
 
@@ -316,13 +375,17 @@ struct Tile {
     }
   }
 
-  __device__ static void activate(const Streams& A, Streams& H) {
+  // GA: a network with another activation than tanh or with trainable
+  // slopes (activation act, effective slope c of the layer); else plain tanh
+  template <bool GA>
+  __device__ static void activate(const Streams& A, Streams& H, int act, float c) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float h, hx, hy, hl;
-        tanh_rule<S2>(A[0][mb][i], A[1][mb][i], A[2][mb][i], A[3][mb][i], h, hx, hy, hl);
+        if constexpr (GA) act_rule<S2>(act, c, A[0][mb][i], A[1][mb][i], A[2][mb][i], A[3][mb][i], h, hx, hy, hl);
+        else tanh_rule<S2>(A[0][mb][i], A[1][mb][i], A[2][mb][i], A[3][mb][i], h, hx, hy, hl);
         H[0][mb][i] = h;
         H[1][mb][i] = hx;
         H[2][mb][i] = hy;
@@ -359,9 +422,10 @@ struct Tile {
   // block is zero padding and is skipped.
   __device__ static int real_steps(int width) { return (width - (WP - 16) + 3) >> 2; }
 
-  template <bool STASH>
+  template <bool STASH, bool GA>
   __device__ static void hidden_layer(const float* sW, const float* bias, int g, int pc, int rq, const Streams& H,
-                                      Streams& Hn, __amdgpu_buffer_rsrc_t rs, int layer, int wave, int lane) {
+                                      Streams& Hn, __amdgpu_buffer_rsrc_t rs, int layer, int wave, int lane, int act,
+                                      float c) {
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       f4 acc[4];
@@ -387,7 +451,8 @@ struct Tile {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float h, hx, hy, hl;
-        tanh_rule<S2>(acc[0][i], acc[1][i], acc[2][i], acc[3][i], h, hx, hy, hl);
+        if constexpr (GA) act_rule<S2>(act, c, acc[0][i], acc[1][i], acc[2][i], acc[3][i], h, hx, hy, hl);
+        else tanh_rule<S2>(acc[0][i], acc[1][i], acc[2][i], acc[3][i], h, hx, hy, hl);
         Hn[0][mb][i] = h;
         Hn[1][mb][i] = hx;
         Hn[2][mb][i] = hy;
@@ -611,9 +676,16 @@ struct Tile {
   //               network (the K-network of the inverse problem);
   //  VAL_INV_NB   (u, K, L(u, K)) of a neighbour's u-network, with its K streams
   //               read from kin.
-  template <int VMODE>
-  __device__ __forceinline__ static void values_tile(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* dst,
-                                     const float* kin, int t0) {
+  // effective slope c_k = n a^k of hidden layer k (1 unless adaptive)
+  __device__ static float slope(const NetDesc& nd, const float* K, const Layout& L, int k) {
+    return nd.adaptive ? K[L.k_slope() + k - 1] : 1.f;
+  }
+
+  // GA: the general activation rule (any activation, trainable slopes);
+  // for a tanh network without slopes it gives the plain rule's values
+  template <int VMODE, bool GA>
+  __device__ __forceinline__ static void values_tile(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
+                                                     float* dst, const float* kin, int t0) {
     float* sW = lds;
     const int tid = item_tid();
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -630,7 +702,7 @@ struct Tile {
     {
       Streams A;
       layer1(K, x, y, g, A);
-      activate(A, H);
+      activate<GA>(A, H, nd.act, slope(nd, K, L, 1));
     }
     const __amdgpu_buffer_rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(lds, 0, 0, 0x00020000);  // unused
     for (int k = 2; k <= nd.depth; ++k) {
@@ -638,7 +710,8 @@ struct Tile {
       stage_wb(sW, K + L.k_w(k), K + L.k_b(k), tid);
       __syncthreads();
       Streams Hn;
-      hidden_layer<false>(sW, sW + WP * WS, g, pc, real_steps(nd.width), H, Hn, none, 0, wave, lane);
+      hidden_layer<false, GA>(sW, sW + WP * WS, g, pc, real_steps(nd.width), H, Hn, none, 0, wave, lane, nd.act,
+                              slope(nd, K, L, k));
 #pragma unroll
       for (int st = 0; st < 4; ++st)
 #pragma unroll
@@ -673,7 +746,14 @@ struct Tile {
   // offset of this network's part in the item's gradient row; MODE selects the
   // epilogue (sInv: the LDS exchange area of the inverse problem); PHASE the
   // parts run.  slot is this network's stash (slot_floats long).
-  template <bool PREFETCH_A, int MODE, int PHASE>
+  // Sum of dc over the wave's lanes into sSl[wave] (a fixed butterfly).
+  __device__ static void slope_wave_sum(float dc, float* sSl, int lane, int wave) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) dc += __shfl_xor(dc, m);
+    if (lane == 0) sSl[wave] = dc;
+  }
+
+  template <bool PREFETCH_A, int MODE, int PHASE, bool GA>
   __device__ __forceinline__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                    float* slot, int64_t slot_floats, const float* sNb, float* sInv, int t_lo,
                                    int t_hi, int roff) {
@@ -683,6 +763,7 @@ struct Tile {
     float* sU = sH + WP * TPS;       // [4 streams][3 outputs][TP]
     float* sX = sU + 4 * 3 * TP;     // [2][TP]
     float* sRed = sX + 2 * TP;       // [kWaves][kLossTerms]
+    float* sSl = sRed + kWaves * kLossTerms;   // [kWaves] slope-gradient sums
     const int D = nd.depth;
     const Layout L(WP, D, DO);
     const float* K = ka.kparams + nd.koff;
@@ -719,7 +800,7 @@ struct Tile {
         Streams A;
         if (PHASE == PH_BWD && D >= 2) stash_load(rs, 0, D - 2, wave, lane, A);
         else layer1(K, x, y, g, A);
-        activate(A, H);
+        activate<GA>(A, H, nd.act, slope(nd, K, L, PHASE == PH_BWD && D >= 2 ? D : 1));
       }
       for (int k = 2; k <= (PHASE == PH_BWD ? 1 : D); ++k) {
         tid = item_tid();
@@ -733,8 +814,8 @@ struct Tile {
         stage_wb(sW, K + L.k_w(k), K + L.k_b(k), tid);
         __syncthreads();
         Streams Hn;
-        hidden_layer<true>(sW, sW + WP * WS, g, pc, real_steps(nd.width), H, Hn, rs, k - 2, wave,
-                           lane);   // stashes a^k
+        hidden_layer<true, GA>(sW, sW + WP * WS, g, pc, real_steps(nd.width), H, Hn, rs, k - 2, wave, lane,
+                               nd.act, slope(nd, K, L, k));   // stashes a^k
 #pragma unroll
         for (int st = 0; st < 4; ++st)
 #pragma unroll
@@ -870,27 +951,38 @@ struct Tile {
           }
         }
         float dbias = tid < WP ? prior(R + L.g_b(k) + tid, first) : 0.f;
-        // abar^k from the stashed a^k (loaded ahead) and the incoming g^k (in place of g^k)
+        // abar^k from the stashed a^k (loaded ahead) and the incoming g^k (in place
+        // of g^k); with a general activation also the layer's slope gradient
         {
           if (!PREFETCH_A) stash_load(rs, 0, k - 2, wave, lane, Ak);
+          const float ck = GA ? slope(nd, K, L, k) : 1.f;
+          float dc = 0.f;
 #pragma unroll
           for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               float a0, a1, a2, a3;
-              tanh_adj<S2>(Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i], G[0][mb][i], G[1][mb][i],
-                           G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
+              if constexpr (GA)
+                act_adj<S2>(nd.act, ck, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i], G[0][mb][i],
+                            G[1][mb][i], G[2][mb][i], G[3][mb][i], a0, a1, a2, a3, dc);
+              else
+                tanh_adj<S2>(Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i], G[0][mb][i], G[1][mb][i],
+                             G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
               G[0][mb][i] = a0;
               G[1][mb][i] = a1;
               G[2][mb][i] = a2;
               G[3][mb][i] = a3;
             }
           }
+          if constexpr (GA) slope_wave_sum(dc, sSl, lane, wave);
         }
         Streams& Ab = G;
         __syncthreads();
         stage(sW, K + L.k_wt(k), tid);
         __syncthreads();
+        if constexpr (GA) {
+          if (nd.adaptive && tid == 0) accum(R + L.g_slope() + k - 1, (sSl[0] + sSl[1]) + (sSl[2] + sSl[3]), first);
+        }
         // per stream: g^{k-1}_s = W^{kT} abar^k_s, then the stream's share of
         // dW^k = sum_{points, streams} abar^k h^{k-1 T}; db^k = sum_points abar^k_0.
         // The barrier that frees sA/sH from the previous stream's dW comes after
@@ -957,13 +1049,19 @@ struct Tile {
         Streams A1;
         layer1(K, x, y, g, A1);
         __syncthreads();
+        const float c1 = GA ? slope(nd, K, L, 1) : 1.f;
+        float dc = 0.f;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             float a0, a1, a2, a3;
-            tanh_adj<S2>(A1[0][mb][i], A1[1][mb][i], A1[2][mb][i], A1[3][mb][i], G[0][mb][i], G[1][mb][i],
-                         G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
+            if constexpr (GA)
+              act_adj<S2>(nd.act, c1, A1[0][mb][i], A1[1][mb][i], A1[2][mb][i], A1[3][mb][i], G[0][mb][i],
+                          G[1][mb][i], G[2][mb][i], G[3][mb][i], a0, a1, a2, a3, dc);
+            else
+              tanh_adj<S2>(A1[0][mb][i], A1[1][mb][i], A1[2][mb][i], A1[3][mb][i], G[0][mb][i], G[1][mb][i],
+                           G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
             // abar^1 streams: value to sA, d/dz0 to sH, d/dz1 to sW where the
             // staged-weight buffer (free in this block) holds WP x TPS floats
             sA[(16 * mb + 4 * g + i) * TPS + tp] = a0;
@@ -972,7 +1070,11 @@ struct Tile {
             else G[2][mb][i] = a2;
           }
         }
+        if constexpr (GA) slope_wave_sum(dc, sSl, lane, wave);
         __syncthreads();
+        if constexpr (GA) {
+          if (nd.adaptive && tid == 0) accum(R + L.g_slope(), (sSl[0] + sSl[1]) + (sSl[2] + sSl[3]), first);
+        }
         float dw0 = 0.f, dw1 = 0.f, db = 0.f;
         if (tid < WP) {
           dw0 = row_dot_plus(sA + tid * TPS, sX, sH + tid * TPS);
@@ -1000,21 +1102,22 @@ struct Tile {
   // entry from a kernel built for classes up to WPMAX: the a^k prefetch costs
   // registers, so it is used for classes up to 48 in kernels that run two
   // waves per SIMD anyway because of a wider class
-  template <int WPMAX, int MODE, int PHASE = PH_ALL>
+  // (GA as in values_tile)
+  template <int WPMAX, int MODE, int PHASE, bool GA>
   __device__ __forceinline__ static void train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* slot,
                                int64_t slot_floats, const float* sNb, float* sInv, int t_lo, int t_hi, int roff) {
-    run_train<(WP <= 48 && WPMAX >= 48), MODE, PHASE>(ka, it, nd, lds, slot, slot_floats, sNb, sInv, t_lo, t_hi,
-                                                       roff);
+    run_train<(WP <= 48 && WPMAX >= 48), MODE, PHASE, GA>(ka, it, nd, lds, slot, slot_floats, sNb, sInv, t_lo, t_hi,
+                                                           roff);
   }
 };
 
 // LDS floats of a train kernel for classes up to WP: the tile buffers of
-// Tile<WP> (sW, sA, sH, sU, sX, sRed), then the neighbour values sNb (6 per
+// Tile<WP> (sW, sA, sH, sU, sX, sRed, sSl), then the neighbour values sNb (6 per
 // point), then for the inverse problem 9 per point: the own K streams, the K
 // seeds, the neighbour's K streams.
 template <int WP, int PDE>
 constexpr int lds_tile_floats() {
-  return WP * (WP + 4) + WP + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms;
+  return WP * (WP + 4) + WP + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms + kWaves;
 }
 template <int WP, int PDE>
 constexpr int lds_train_floats() {
@@ -1033,7 +1136,7 @@ constexpr int lds_train_bytes() {
 // A paired item of the inverse problem goes tile by tile: the neighbour's K-
 // and u-networks (interfaces), the own K-network's streams, the u-network's
 // train pass (loss, u seeds, K seeds), then the K-network's train pass.
-template <int WPMAX, int PDE>
+template <int WPMAX, int PDE, bool GA>
 __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                          float* slot) {
   float* sNb = lds + lds_tile_floats<WPMAX, PDE>();
@@ -1069,17 +1172,18 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
       for (int t0 = 0; t0 < it.count; t0 += TP) {
         __syncthreads();
         if (it.kind == KIND_IFACE) {
-          DDP_SWITCH(nbk.wclass, template values_tile<VAL_STREAMS>(ka, it, nbk, lds, sInv + 6 * TP, nullptr, t0))
+          DDP_SWITCH(nbk.wclass,
+                     template values_tile<VAL_STREAMS, GA>(ka, it, nbk, lds, sInv + 6 * TP, nullptr, t0))
           __syncthreads();
-          DDP_SWITCH(nbu.wclass, template values_tile<VAL_INV_NB>(ka, it, nbu, lds, sNb, sInv + 6 * TP, t0))
+          DDP_SWITCH(nbu.wclass, template values_tile<VAL_INV_NB, GA>(ka, it, nbu, lds, sNb, sInv + 6 * TP, t0))
           __syncthreads();
         }
-        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_FWD>(ka, it, ndk, lds, slot + half, half, sNb,
-                                                                        sInv, t0, t0 + 1, nd.gsize))
+        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_FWD, GA>(ka, it, ndk, lds, slot + half, half,
+                                                                            sNb, sInv, t0, t0 + 1, nd.gsize))
         DDP_SWITCH(nd.wclass,
-                   template train<WPMAX, EPI_INV_U>(ka, it, nd, lds, slot, half, sNb, sInv, t0, t0 + 1, 0))
-        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_BWD>(ka, it, ndk, lds, slot + half, half, sNb,
-                                                                        sInv, t0, t0 + 1, nd.gsize))
+                   template train<WPMAX, EPI_INV_U, PH_ALL, GA>(ka, it, nd, lds, slot, half, sNb, sInv, t0, t0 + 1, 0))
+        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_BWD, GA>(ka, it, ndk, lds, slot + half, half,
+                                                                            sNb, sInv, t0, t0 + 1, nd.gsize))
       }
       return;
     }
@@ -1087,10 +1191,10 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
     const IfaceDesc ifd = ka.ifaces[it.iface];
     const NetDesc ndn = ka.nets[it.side == 0 ? ifd.b_net : ifd.a_net];
     __syncthreads();
-    DDP_SWITCH(ndn.wclass, template values_tile<VAL_OWN>(ka, it, ndn, lds, sNb, nullptr, 0))
+    DDP_SWITCH(ndn.wclass, template values_tile<VAL_OWN, GA>(ka, it, ndn, lds, sNb, nullptr, 0))
     __syncthreads();
   }
-  DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_OWN>(ka, it, nd, lds, slot,
+  DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_OWN, PH_ALL, GA>(ka, it, nd, lds, slot,
                                                        PDE == PDE_INV ? ka.scratch_slot / 2 : ka.scratch_slot, sNb,
                                                        sInv, 0, it.count, 0))
 #undef DDP_SWITCH
@@ -1106,7 +1210,10 @@ constexpr int min_waves_per_eu() {
   return WPMAX <= 80 ? 2 : 1;
 }
 
-template <int WPMAX, int PDE>
+// GA: kernels with the general activation rule, launched for problems where a
+// network uses another activation than tanh or trainable slopes (built for
+// the class groups up to 80 and up to 112 only)
+template <int WPMAX, int PDE, bool GA>
 __global__ __launch_bounds__(NT, min_waves_per_eu<WPMAX>()) void k_train(KArgs ka) {
   // one 16-byte aligned dynamic LDS block: the tile buffers, then the slot
   // that broadcasts the next work item (no static LDS, so the float4
@@ -1127,7 +1234,7 @@ __global__ __launch_bounds__(NT, min_waves_per_eu<WPMAX>()) void k_train(KArgs k
     if (idx >= ka.n_items) break;
     const Item it = ka.items[idx];
     const NetDesc nd = ka.nets[it.q];
-    dispatch<WPMAX, PDE>(ka, it, nd, lds, slot);
+    dispatch<WPMAX, PDE, GA>(ka, it, nd, lds, slot);
   }
 }
 
@@ -1141,11 +1248,14 @@ __host__ __device__ __forceinline__ int neuron_pos(int n) { return (n & ~15) | (
 
 // Position of canonical parameter li of a network in its gradient partial row
 // (g) and in its kernel-layout copy (k1, and k2 for the transposed copy of a
-// hidden weight, else -1).
-__device__ __forceinline__ void param_map(const NetDesc& nd, int li, int& g, int& k1, int& k2) {
+// hidden weight, else -1).  sc: the kernel copy holds sc times the parameter
+// and the partial rows hold the gradient divided by sc (n for a slope a^k,
+// whose kernel copy is c_k = n a^k; 1 otherwise).
+__device__ __forceinline__ void param_map(const NetDesc& nd, int li, int& g, int& k1, int& k2, float& sc) {
   const int w = nd.width, WP = nd.wclass, D = nd.depth, DO = nd.d_out;
   const Layout L(WP, D, DO);
   k2 = -1;
+  sc = 1.f;
   if (li < 2 * w) {                 // W^1[m][c]
     const int m = li >> 1, c = li & 1;
     g = k1 = neuron_pos(m) * 4 + c;
@@ -1178,10 +1288,15 @@ __device__ __forceinline__ void param_map(const NetDesc& nd, int li, int& g, int
     const int c = r / w, j = neuron_pos(r - (r / w) * w);
     g = L.g_out() + c * WP + j;
     k1 = L.k_out() + c * WP + j;
-  } else {
+  } else if (r < DO * w + DO) {
     const int c = r - DO * w;
     g = L.g_bout() + c;
     k1 = L.k_bout() + c;
+  } else {                          // slope a^k of hidden layer k = 1..D
+    const int k = r - DO * w - DO;
+    g = L.g_slope() + k;
+    k1 = L.k_slope() + k;
+    sc = nd.slope_n;
   }
 }
 
@@ -1190,6 +1305,11 @@ __device__ __forceinline__ int find_net(const int64_t* net_poff, int n, int64_t 
   while (net_poff[n + 1] <= i) ++n;
   return n;
 }
+
+// The train kernels of each operator are compiled in a translation unit of
+// their own (DDP_TRAIN_PDE set to the operator), so the build runs them in
+// parallel; the unit without it holds the other kernels and the launchers.
+#ifndef DDP_TRAIN_PDE
 
 // Sum each network's gradient partial rows in a fixed order, then write the
 // gradient and/or apply Adam (Kingma-Ba, bias corrected) and refresh the
@@ -1212,7 +1332,8 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
     const int q = find_net(ra.net_poff, ra.net_begin, i);
     const NetDesc nd = ra.nets[q];
     int gi, k1, k2;
-    param_map(nd, (int)(i - ra.net_poff[q]), gi, k1, k2);
+    float sc;
+    param_map(nd, (int)(i - ra.net_poff[q]), gi, k1, k2, sc);
     const int r0 = ra.net_row_ptr[q], n = ra.net_row_ptr[q + 1] - r0;
     const int64_t* pr = ra.row_prow + r0;
     const float* P = ra.partial + gi;
@@ -1231,7 +1352,7 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
     for (int w = kRedLanes / 2; w >= 1; w /= 2)
 #pragma unroll
       for (int j = 0; j < w; ++j) a[j] += a[j + w];
-    const float s = a[0];
+    const float s = sc * a[0];
     if (ra.grad_out) ra.grad_out[i] = s;
     if (ra.do_adam) {
       const float m = b1 * ra.adam_m[i] + (1.f - b1) * s;
@@ -1243,7 +1364,7 @@ __global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
       const float th = ra.params[i] - nd.lr * mh / (sqrtf(vh) + eps);
       ra.params[i] = th;
       float* K = ra.kparams + nd.koff;
-      K[k1] = th;
+      K[k1] = sc * th;
       if (k2 >= 0) K[k2] = th;
     }
   }
@@ -1288,9 +1409,10 @@ __global__ __launch_bounds__(256) void k_pack(const float* params, float* kparam
     const int q = find_net(net_poff, n_begin, i);
     const NetDesc nd = nets[q];
     int gi, k1, k2;
-    param_map(nd, (int)(i - net_poff[q]), gi, k1, k2);
+    float sc;
+    param_map(nd, (int)(i - net_poff[q]), gi, k1, k2, sc);
     float* K = kparams + nd.koff;
-    K[k1] = params[i];
+    K[k1] = sc * params[i];
     if (k2 >= 0) K[k2] = params[i];
   }
 }
@@ -1315,13 +1437,19 @@ __global__ __launch_bounds__(256) void k_eval(const float* params, const NetDesc
       const NetDesc nd = nets[net];
       const float* P = params + nd.poff;
       const int w = nd.width;
-      for (int m = 0; m < w; ++m) h[m] = tanhf(fmaf(P[2 * m], x, fmaf(P[2 * m + 1], y, P[2 * w + m])));
+      // slopes follow the output layer in the canonical layout
+      const float* Sl = P + 3 * w + (int64_t)(nd.depth - 1) * (w * w + w) + nd.d_out * w + nd.d_out;
+      auto phi = [&](float a, int k) {
+        const float yv = nd.adaptive ? nd.slope_n * Sl[k - 1] * a : a;
+        return nd.act == ACT_SIN ? sinf(yv) : nd.act == ACT_COS ? cosf(yv) : tanhf(yv);
+      };
+      for (int m = 0; m < w; ++m) h[m] = phi(fmaf(P[2 * m], x, fmaf(P[2 * m + 1], y, P[2 * w + m])), 1);
       int64_t off = 3 * w;
       for (int k = 2; k <= nd.depth; ++k) {
         for (int m = 0; m < w; ++m) {
           float a = P[off + w * w + m];
           for (int j = 0; j < w; ++j) a = fmaf(P[off + m * w + j], h[j], a);
-          h2[m] = tanhf(a);
+          h2[m] = phi(a, k);
         }
         for (int m = 0; m < w; ++m) h[m] = h2[m];
         off += w * w + w;
@@ -1336,7 +1464,8 @@ __global__ __launch_bounds__(256) void k_eval(const float* params, const NetDesc
   for (int c = 0; c < n_cols; ++c) out[(int64_t)i * n_cols + c] = cnt ? acc[c] / cnt : 0.f;
 }
 
-#ifndef DDP_KERNELS_ONLY
+#endif  // DDP_TRAIN_PDE
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 
@@ -1356,26 +1485,60 @@ static int wclass_index(int wpmax) {
 template <int PDE>
 struct KTable {
   static const void* train[7];
+  static const void* train_ga[2];   // general activation: class groups up to 80, up to 112
   static int lds[7];
 };
-#define DDP_ROW(PDE)                                                                            \
-  template <> const void* KTable<PDE>::train[7] = {                                             \
-      (const void*)k_train<16, PDE>, (const void*)k_train<32, PDE>, (const void*)k_train<48, PDE>, \
-      (const void*)k_train<64, PDE>, (const void*)k_train<80, PDE>, (const void*)k_train<96, PDE>, \
-      (const void*)k_train<112, PDE>};                                                          \
+// (a unit built with DDP_TRAIN_GA defines the general-activation row of its
+// operator, one without it the plain row and the LDS sizes)
+#ifdef DDP_TRAIN_GA
+#define DDP_ROW(PDE)                                                                                              \
+  template <> const void* KTable<PDE>::train_ga[2] = {(const void*)k_train<80, PDE, true>,                        \
+                                                      (const void*)k_train<112, PDE, true>};
+#else
+#define DDP_ROW(PDE)                                                                                              \
+  template <> const void* KTable<PDE>::train[7] = {                                                               \
+      (const void*)k_train<16, PDE, false>, (const void*)k_train<32, PDE, false>,                                 \
+      (const void*)k_train<48, PDE, false>, (const void*)k_train<64, PDE, false>,                                 \
+      (const void*)k_train<80, PDE, false>, (const void*)k_train<96, PDE, false>,                                 \
+      (const void*)k_train<112, PDE, false>};                                                                     \
   template <> int KTable<PDE>::lds[7] = {                                                       \
       lds_train_bytes<16, PDE>(), lds_train_bytes<32, PDE>(), lds_train_bytes<48, PDE>(),       \
       lds_train_bytes<64, PDE>(), lds_train_bytes<80, PDE>(), lds_train_bytes<96, PDE>(),       \
       lds_train_bytes<112, PDE>()};
-DDP_ROW(PDE_POISSON)
-DDP_ROW(PDE_BURGERS)
-DDP_ROW(PDE_NS)
-DDP_ROW(PDE_INV)
+#endif
+#ifdef DDP_TRAIN_PDE
+DDP_ROW(DDP_TRAIN_PDE)
 #undef DDP_ROW
+#else
+#undef DDP_ROW
+// the tables are defined in the operators' own translation units
+template <> const void* KTable<PDE_POISSON>::train[7];
+template <> const void* KTable<PDE_BURGERS>::train[7];
+template <> const void* KTable<PDE_NS>::train[7];
+template <> const void* KTable<PDE_INV>::train[7];
+template <> const void* KTable<PDE_POISSON>::train_ga[2];
+template <> const void* KTable<PDE_BURGERS>::train_ga[2];
+template <> const void* KTable<PDE_NS>::train_ga[2];
+template <> const void* KTable<PDE_INV>::train_ga[2];
+template <> int KTable<PDE_POISSON>::lds[7];
+template <> int KTable<PDE_BURGERS>::lds[7];
+template <> int KTable<PDE_NS>::lds[7];
+template <> int KTable<PDE_INV>::lds[7];
 
-static const void* pick(int pde, int wpmax) {
+static const void* pick(int pde, int wpmax, bool ga) {
   const int c = wclass_index(wpmax);
   if (c < 0) return nullptr;
+  if (ga) {   // general-activation kernels exist for the groups up to 80 and up to 112
+    if (wpmax != 80 && wpmax != 112) return nullptr;
+    const int g = wpmax == 80 ? 0 : 1;
+    switch (pde) {
+      case PDE_POISSON: return KTable<PDE_POISSON>::train_ga[g];
+      case PDE_BURGERS: return KTable<PDE_BURGERS>::train_ga[g];
+      case PDE_NS: return KTable<PDE_NS>::train_ga[g];
+      case PDE_INV: return KTable<PDE_INV>::train_ga[g];
+    }
+    return nullptr;
+  }
   switch (pde) {
     case PDE_POISSON: return KTable<PDE_POISSON>::train[c];
     case PDE_BURGERS: return KTable<PDE_BURGERS>::train[c];
@@ -1405,16 +1568,18 @@ int64_t scratch_slot_floats(int pde, int wpmax) {
   return pde == PDE_INV ? 2 * one : one;
 }
 
-hipError_t launch_train(int pde, int wpmax, const KArgs& ka, int grid, hipStream_t st) {
-  const void* fn = pick(pde, wpmax);
+int kernel_wpmax(int wpmax, bool ga) { return ga ? (wpmax <= 80 ? 80 : 112) : wpmax; }
+
+hipError_t launch_train(int pde, int wpmax, bool ga, const KArgs& ka, int grid, hipStream_t st) {
+  const void* fn = pick(pde, wpmax, ga);
   if (!fn) return hipErrorInvalidValue;
   KArgs a = ka;
   void* args[] = {&a};
   return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds_bytes(pde, wpmax), st);
 }
 
-hipError_t train_occupancy(int pde, int wpmax, int* blocks_per_cu) {
-  const void* fn = pick(pde, wpmax);
+hipError_t train_occupancy(int pde, int wpmax, bool ga, int* blocks_per_cu) {
+  const void* fn = pick(pde, wpmax, ga);
   if (!fn) return hipErrorInvalidValue;
   const size_t lds = lds_bytes(pde, wpmax);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1448,5 +1613,5 @@ hipError_t launch_eval(const float* params, const NetDesc* nets, const int* sd_n
   return hipGetLastError();
 }
 
-#endif  // DDP_KERNELS_ONLY
+#endif  // DDP_TRAIN_PDE
 }  // namespace ddp

@@ -22,9 +22,12 @@ DDP_CPINN, DDP_XPINN = 0, 1
 DDP_POISSON2D, DDP_BURGERS1D, DDP_NS2D_STEADY, DDP_DIFFUSION2D_INV = 0, 1, 2, 3
 DDP_RESIDUAL, DDP_DATA, DDP_DATA_AUX = 0, 1, 2
 DDP_OPT_CHUNK_POINTS, DDP_OPT_BLOCKS_PER_CU, DDP_OPT_ITEMS_PER_SLOT = 0, 1, 2
+DDP_ACT_TANH, DDP_ACT_SIN, DDP_ACT_COS = 0, 1, 2
+_ACT = {"tanh": DDP_ACT_TANH, "sin": DDP_ACT_SIN, "cos": DDP_ACT_COS}
 
 EXPORTED = [
     "ddp_create", "ddp_add_subdomain", "ddp_set_points", "ddp_add_interface", "ddp_set_interface_method",
+    "ddp_set_activation",
     "ddp_set_option",
     "ddp_finalize", "ddp_param_count", "ddp_set_params", "ddp_get_params", "ddp_loss_and_grad",
     "ddp_step", "ddp_get_state", "ddp_set_state", "ddp_eval", "ddp_sync", "ddp_time_kernels",
@@ -60,6 +63,7 @@ def load_library(path=LIB_PATH):
         "ddp_set_points": ([P, I, I, I, P, P, I], I),
         "ddp_add_interface": ([P, I, I, I, P, pF, I, pI], I),
         "ddp_set_interface_method": ([P, I, I], I),
+        "ddp_set_activation": ([P, I, I, I, F], I),
         "ddp_set_option": ([P, I, I64], I),
         "ddp_finalize": ([P, P, I], I),
         "ddp_param_count": ([P, I, pI64], I),
@@ -137,6 +141,10 @@ class Problem:
                 if s.aux_widths is not None:
                     ax, ag = _host_f32(s.aux_xy), _host_f32(s.aux_g)
                     _check(L.ddp_set_points(self._h, sid.value, DDP_DATA_AUX, ax.shape[0], _ptr(ax), _ptr(ag), 0))
+                act, adaptive = getattr(s, "act", "tanh"), bool(getattr(s, "adaptive", False))
+                if act != "tanh" or adaptive:
+                    _check(L.ddp_set_activation(self._h, sid.value, _ACT[act], int(adaptive),
+                                                float(getattr(s, "slope_n", 10.0))))
             for e in prob.interfaces:
                 xy = _host_f32(e.xy)
                 nrm = (ctypes.c_float * 2)(*[float(v) for v in e.normal])

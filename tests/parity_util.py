@@ -9,9 +9,10 @@ LOSS_RTOL = 1e-5
 GRAD_RTOL = 1e-5
 
 
-def layer_slices(widths, aux_widths=None):
-    """Slices of every weight matrix and bias vector in a subdomain's flat
-    parameters (the u-network, then the K-network of the inverse problem)."""
+def layer_slices(widths, aux_widths=None, adaptive=False):
+    """Slices of every weight matrix and bias vector (and of an adaptive
+    network's slopes) in a subdomain's flat parameters (the u-network, then
+    the K-network of the inverse problem)."""
     out, off = [], 0
     for wd in [widths] + ([aux_widths] if aux_widths is not None else []):
         for k in range(1, len(wd)):
@@ -20,6 +21,9 @@ def layer_slices(widths, aux_widths=None):
             off += n
             out.append(slice(off, off + wd[k]))
             off += wd[k]
+        if adaptive:
+            out.append(slice(off, off + len(wd) - 2))
+            off += len(wd) - 2
     return out
 
 
@@ -45,7 +49,7 @@ def compare(prob, params, lt_gpu, g_gpu, loss_rtol=LOSS_RTOL, grad_rtol=GRAD_RTO
         assert err <= grad_rtol, f"sd {q} grad rel {err:.3e} (|g|={nref:.3e})"
         if per_layer:
             sd = prob.subdomains[q]
-            for k, sl in enumerate(layer_slices(sd.widths, sd.aux_widths)):
+            for k, sl in enumerate(layer_slices(sd.widths, sd.aux_widths, getattr(sd, "adaptive", False))):
                 r = ref[sl]
                 nr = np.linalg.norm(r)
                 if nr == 0.0 or nr < 1e-6 * nref:   # (a zero gradient is checked as a whole above)

@@ -44,7 +44,7 @@ def _item_cost(nets, q, kind, count):
 
 @pytest.mark.parametrize("name", ["c1_cpinn_poisson", "c2_xpinn_poisson", "c3_cpinn_burgers", "c4_xpinn_kovasznay",
                                   "c5_xpinn_inverse_diffusion", "burgers_st_xpinn_4x4", "burgers_st_cpinn_32x1",
-                                  "burgers_st_hybrid_4x4", "ns_cpinn_kovasznay"])
+                                  "burgers_st_hybrid_4x4", "ns_cpinn_kovasznay", "c5_table4_adaptive"])
 def test_plan_covers_every_point_once(name, tmp_path):
     prob = W.make_problem(name, seed=0, scale=0.05 if name.startswith("c5") else 0.3)
     d = _plan(prob, tmp_path, chunk_points=100)
@@ -58,6 +58,17 @@ def test_plan_covers_every_point_once(name, tmp_path):
         for b, c in zip(begin[kind == k], count[kind == k]):
             cover[b:b + c] += 1
         assert (cover == 1).all()
+    # activations; a problem with a general activation runs the kernels of
+    # the class groups up to 80 and up to 112
+    acts = {"tanh": 0, "sin": 1, "cos": 2}
+    want_act = []
+    for s in prob.subdomains:
+        want_act += [(acts[s.act], int(s.adaptive))] * (1 if s.aux_widths is None else 2)
+    assert [(n["act"], n["adaptive"]) for n in nets] == want_act
+    assert [n["n_params"] for n in nets] == [W.param_count(wd, s.adaptive) for s in prob.subdomains
+                                             for wd in ([s.widths] + ([s.aux_widths] if s.aux_widths else []))]
+    if any(a != (0, 0) for a in want_act):
+        assert all(l["wpmax"] in (80, 112) for l in d["launches"])
     # each interface keeps its own condition (the problem's unless set)
     want = [ddpinn._METHOD[e.method or prob.method] for e in prob.interfaces]
     assert [e["method"] for e in d["ifaces"]] == want
@@ -112,11 +123,11 @@ def test_plan_covers_every_point_once(name, tmp_path):
     sd_net = d["sd_net"]
     for sd, s in enumerate(prob.subdomains):
         u = nets[sd_net[sd]]
-        assert u["n_params"] == W.param_count(s.widths) and u["sd"] == sd
+        assert u["n_params"] == W.param_count(s.widths, s.adaptive) and u["sd"] == sd
         assert u["wclass"] % 16 == 0 and u["wclass"] >= s.widths[1]
         if s.aux_widths is not None:
             k = nets[sd_net[sd] + 1]
-            assert u["pair"] == sd_net[sd] + 1 and k["n_params"] == W.param_count(s.aux_widths)
+            assert u["pair"] == sd_net[sd] + 1 and k["n_params"] == W.param_count(s.aux_widths, s.adaptive)
             assert k["poff"] == u["poff"] + u["n_params"]
         assert sd_net[sd + 1] - sd_net[sd] == (2 if s.aux_widths is not None else 1)
 
@@ -158,6 +169,18 @@ def test_input_validation_codes():
     assert L.ddp_set_interface_method(h, 1, ddpinn.DDP_CPINN) == ddpinn.DDP_EINVAL   # unknown interface
     assert L.ddp_set_interface_method(h, 0, 2) == ddpinn.DDP_EINVAL                  # unknown method
     assert L.ddp_set_interface_method(h, 0, ddpinn.DDP_CPINN) == 0
+    # activation: validation, and D slopes per network once adaptive
+    n = ct.c_int64()
+    assert L.ddp_param_count(h, 1, ct.byref(n)) == 0 and n.value == W.param_count([2, 8, 8, 1])
+    assert L.ddp_set_activation(h, 2, ddpinn.DDP_ACT_SIN, 1, 10.0) == ddpinn.DDP_EINVAL   # unknown subdomain
+    assert L.ddp_set_activation(h, 1, 3, 1, 10.0) == ddpinn.DDP_EINVAL                    # unknown activation
+    assert L.ddp_set_activation(h, 1, ddpinn.DDP_ACT_SIN, 2, 10.0) == ddpinn.DDP_EINVAL
+    assert L.ddp_set_activation(h, 1, ddpinn.DDP_ACT_SIN, 1, 0.0) == ddpinn.DDP_EINVAL
+    assert L.ddp_set_activation(h, 1, ddpinn.DDP_ACT_SIN, 1, float("nan")) == ddpinn.DDP_EINVAL
+    assert L.ddp_set_activation(h, 1, ddpinn.DDP_ACT_COS, 1, 10.0) == 0
+    assert L.ddp_param_count(h, 1, ct.byref(n)) == 0 and n.value == W.param_count([2, 8, 8, 1]) + 2
+    assert L.ddp_set_activation(h, 1, ddpinn.DDP_ACT_SIN, 0, 10.0) == 0
+    assert L.ddp_param_count(h, 1, ct.byref(n)) == 0 and n.value == W.param_count([2, 8, 8, 1])
     assert L.ddp_set_option(h, 99, 1) == ddpinn.DDP_EINVAL
     # calls that need a finalized problem
     assert L.ddp_step(h, 1, None) == ddpinn.DDP_ESTATE

@@ -481,3 +481,114 @@ def test_space_time_burgers_hybrid(seed):
     wl, wg = compare(prob, params, lt, g)
     _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
     pb.close()
+
+
+# ---------------------------------------------------------------------------
+# activation choice and trainable slopes (Sec. 3, Table 4)
+
+
+def _slope_identity_gaps(sd, theta, grad):
+    """a^k dJ/da^k - (<W^k, dJ/dW^k> + <b^k, dJ/db^k>) relative to the terms'
+    size, for every hidden layer of each of the subdomain's networks."""
+    gaps, off = [], 0
+    th, g = theta.astype(np.float64), grad.astype(np.float64)
+    for wd in [sd.widths] + ([sd.aux_widths] if sd.aux_widths is not None else []):
+        lay = []
+        for k in range(1, len(wd)):
+            n = wd[k] * wd[k - 1] + wd[k]
+            lay.append(slice(off, off + n))
+            off += n
+        for k in range(len(wd) - 2):
+            lhs = th[off + k] * g[off + k]
+            prod = th[lay[k]] * g[lay[k]]
+            gaps.append(abs(lhs - prod.sum()) / max(np.abs(prod).sum(), 1e-30))
+        off += len(wd) - 2
+    return gaps
+
+
+@pytest.mark.parametrize("scale,seed", [(0.05, 91), (1.0, None)])
+def test_table4_adaptive_inverse(scale, seed):
+    """The inverse problem with Table 4's networks (adaptive tanh / sin / cos
+    per subdomain, 3 x 80 for u and K): loss terms and gradients, slopes
+    included, against the oracle; at full size also the slope identity of
+    every layer on the GPU's own gradient."""
+    prob = W.c5_table4_adaptive(seed=0, scale=scale)
+    params = _params(prob, seed)
+    _say(f"table 4 adaptive scale {scale} perturbation {seed}")
+    pb, lt, g = run(prob, params)
+    wl, wg = compare(prob, params, lt, g)
+    _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+    if scale == 1.0:
+        worst = max(max(_slope_identity_gaps(s, params[q], g[q])) for q, s in enumerate(prob.subdomains))
+        _say(f"  slope identity worst {worst:.2e}")
+        assert worst < 1e-4
+    pb.close()
+
+
+def _mixed_activation_problem(method, pde):
+    """2 x 2 boxes across width classes: a plain tanh network, then adaptive
+    sin, cos and tanh networks (neighbours of different kinds)."""
+    if pde == "poisson2d":
+        widths = [[2, 20, 20, 1], [2, 40, 40, 40, 1], [2, 64, 64, 1], [2, 96, 96, 96, 1]]
+        prob = W.custom_box_problem(method, pde, 2, 2, widths, [65, 130, 1, 200], n_bnd_seg=7, n_iface=67, seed=12)
+    else:
+        widths = [[2, 17, 17, 3], [2, 48, 48, 3], [2, 33, 33, 33, 3], [2, 80, 80, 3]]
+        prob = W.custom_box_problem(method, pde, 2, 2, widths, [70, 64, 129, 90], n_bnd_seg=5, n_iface=41, seed=13,
+                                    coef=(40.0,), domain=(-0.5, 1.0, -0.5, 1.5))
+    W.with_activations(prob, ("tanh", "sin", "cos", "tanh"))
+    s0 = prob.subdomains[0]
+    s0.adaptive, s0.params = False, s0.params[:W.param_count(s0.widths)].copy()
+    return prob
+
+
+@pytest.mark.parametrize("method,pde", [("xpinn", "poisson2d"), ("cpinn", "poisson2d"), ("cpinn", "ns2d_steady")])
+def test_mixed_activations_across_classes(method, pde):
+    prob = _mixed_activation_problem(method, pde)
+    params = _params(prob, 14)
+    for fused in (True, False):
+        _say(f"mixed activations {method} {pde} fused {fused}")
+        pb, lt, g = run(prob, params, fused=fused, chunk_points=64)
+        wl, wg = compare(prob, params, lt, g)
+        _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+        pb.close()
+
+
+def test_adaptive_sin_burgers_space_time():
+    """Adaptive sin and cos networks on the space-time Burgers problem (only
+    u_xx in the second-order stream)."""
+    prob = W.with_activations(W.burgers_space_time("xpinn", 2, 2, seed=3, scale=0.02), ("sin", "cos"))
+    params = _params(prob, 15)
+    _say("adaptive burgers space-time")
+    pb, lt, g = run(prob, params)
+    compare(prob, params, lt, g)
+    pb.close()
+
+
+def test_table4_eval_adam_and_trajectory():
+    """Stitched evaluation with the activations and slopes, one Adam step
+    (slopes included) and 20 steps of loss history against the oracle."""
+    prob = W.c5_table4_adaptive(seed=1, scale=0.02)
+    params = _params(prob, 16)
+    _say("table 4 eval, Adam step, trajectory")
+    pb = ddpinn.Problem(prob, fused=True)
+    pb.set_params(params)
+    idx = np.arange(0, prob.eval_xy.shape[0], 23)
+    uk = pb.eval(prob.eval_xy[idx], prob.eval_owner[idx]).cpu().numpy()
+    ref = oracle.eval_stitched(prob, params, prob.eval_xy[idx], prob.eval_owner[idx])
+    np.testing.assert_allclose(uk, ref, rtol=1e-5, atol=1e-6)
+    _, grads = oracle.loss_and_grad(prob, params)
+    pb.step(1)
+    got = pb.get_params()
+    for q, s in enumerate(prob.subdomains):
+        th, _, _ = oracle.adam_step(params[q].astype(np.float64), 0.0, 0.0, grads[q], 1, s.lr)
+        step = got[q].astype(np.float64) - params[q].astype(np.float64)
+        ref_step = th - params[q].astype(np.float64)
+        big = np.abs(grads[q]) > 1e-3 * np.abs(grads[q]).max()
+        np.testing.assert_allclose(step[big], ref_step[big], rtol=2e-3, atol=2e-6 * s.lr)
+    pb.close()
+    pb = ddpinn.Problem(prob, fused=True)
+    pb.set_params(params)
+    hist = np.stack([pb.step(1).cpu().numpy().copy() for _ in range(20)])
+    _, hist_ref = oracle.train(prob, params, 20)
+    np.testing.assert_allclose(hist[:, :, 0], hist_ref[:, :, 0], rtol=2e-3)
+    pb.close()
