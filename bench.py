@@ -183,8 +183,13 @@ def main():
         print(f"# plain: {ms_plain:.4f} ms/step", file=sys.stderr, flush=True)
 
     achieved = flops / (kt["train_ms"] * 1e-3) / 1e12
+    # the rate a pure MFMA loop sustains on this device (the part clocks below
+    # its rated 2.4 GHz under full matrix load): the attainable peak
+    probe = ddpinn.mfma_probe(2000)
+    print(f"# mfma probe: {probe:.1f} TFLOP/s", file=sys.stderr, flush=True)
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+            "mfma_probe": probe, "frac_of_probe": achieved / probe if probe > 0 else None,
             "traffic": traffic_from_profile(1) if args.workload == WORKLOAD else None,
             "kernel": "k_train", "kernel_ms": kt["train_ms"], "algorithmic_flop_per_launch": flops}
     out = {

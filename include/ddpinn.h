@@ -205,6 +205,15 @@ int ddp_sync(ddp_problem* p);
  * Leaves parameters and the Adam state unchanged. */
 int ddp_time_kernels(ddp_problem* p, int iters, float* ms);
 
+/* Measurement: the FP32 matrix-core rate the current device sustains, in
+ * TFLOP/s, on a loop of 16x16x4 FP32 MFMAs with no memory traffic (eight
+ * waves per SIMD, iters unrolled steps of four independent MFMAs per wave;
+ * 2000 runs for a few milliseconds).  This attainable peak sits below the
+ * published 157.3 TFLOP/s when the part clocks below 2.4 GHz under load.
+ * Synchronous on the null stream; allocates and frees a small device buffer.
+ * DDP_EINVAL for iters outside 1..2^20 or a null tflops. */
+int ddp_mfma_probe(int iters, double* tflops);
+
 /* Write the packed plan (subdomains, interfaces, work items, offsets) as JSON.
  * Host only; valid after ddp_plan (or ddp_finalize). */
 int ddp_plan_dump(const ddp_problem* p, const char* json_path);

@@ -1125,6 +1125,12 @@ int ddp_sync(ddp_problem* p) {
   return DDP_OK;
 }
 
+int ddp_mfma_probe(int iters, double* tflops) {
+  if (iters < 1 || iters > (1 << 20) || !tflops) return fail(DDP_EINVAL, "bad probe arguments");
+  HIP_TRY(mfma_probe(iters, tflops));
+  return DDP_OK;
+}
+
 int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
   if (int rc = check_final(p)) return rc;
   if (iters < 1 || !ms) return fail(DDP_EINVAL, "bad timing arguments");

@@ -30,4 +30,8 @@ hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets,
 hipError_t launch_eval(const float* params, const NetDesc* nets, const int* sd_net, int n_sd, int n, const float* xy,
                        const int* owner, float* out, int n_cols, hipStream_t st);
 
+// FP32 MFMA rate (TFLOP/s) the device sustains on a pure MFMA loop of iters
+// unrolled steps per wave (probe.hip); synchronous
+hipError_t mfma_probe(int iters, double* tflops);
+
 }  // namespace ddp

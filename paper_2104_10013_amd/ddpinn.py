@@ -31,7 +31,7 @@ EXPORTED = [
     "ddp_set_option",
     "ddp_finalize", "ddp_param_count", "ddp_set_params", "ddp_get_params", "ddp_loss_and_grad",
     "ddp_step", "ddp_get_state", "ddp_set_state", "ddp_eval", "ddp_sync", "ddp_time_kernels",
-    "ddp_plan_dump", "ddp_plan", "ddp_last_error", "ddp_destroy", "ddp_autotune",
+    "ddp_plan_dump", "ddp_plan", "ddp_last_error", "ddp_destroy", "ddp_autotune", "ddp_mfma_probe",
 ]
 
 _METHOD = {W.METHOD_CPINN: DDP_CPINN, W.METHOD_XPINN: DDP_XPINN}
@@ -81,6 +81,7 @@ def load_library(path=LIB_PATH):
         "ddp_last_error": ([], ctypes.c_char_p),
         "ddp_destroy": ([P], I),
         "ddp_autotune": ([P, I, ctypes.c_char_p, pI64], I),
+        "ddp_mfma_probe": ([I, ctypes.POINTER(D)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -88,6 +89,15 @@ def load_library(path=LIB_PATH):
         fn.restype = res
     _lib = L
     return L
+
+
+def mfma_probe(iters=2000):
+    """FP32 MFMA rate (TFLOP/s) the current device sustains on a pure MFMA
+    loop (the attainable matrix-core peak)."""
+    L = load_library()
+    t = ctypes.c_double()
+    _check(L.ddp_mfma_probe(int(iters), ctypes.byref(t)))
+    return t.value
 
 
 def _check(rc):

@@ -26,6 +26,16 @@ def test_library_exports_every_declared_symbol():
     assert sorted(ddpinn.EXPORTED) == decl
 
 
+def test_mfma_probe_rejects_bad_arguments():
+    """Argument checks happen before any GPU call."""
+    import ctypes as ct
+    L = ddpinn.load_library()
+    t = ct.c_double()
+    assert L.ddp_mfma_probe(0, ct.byref(t)) == ddpinn.DDP_EINVAL
+    assert L.ddp_mfma_probe((1 << 20) + 1, ct.byref(t)) == ddpinn.DDP_EINVAL
+    assert L.ddp_mfma_probe(10, None) == ddpinn.DDP_EINVAL
+
+
 def _plan(prob, tmp_path, **kw):
     pb = ddpinn.Problem(prob, plan_only=True, **kw)
     path = tmp_path / "plan.json"

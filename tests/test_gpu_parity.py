@@ -592,3 +592,12 @@ def test_table4_eval_adam_and_trajectory():
     _, hist_ref = oracle.train(prob, params, 20)
     np.testing.assert_allclose(hist[:, :, 0], hist_ref[:, :, 0], rtol=2e-3)
     pb.close()
+
+
+def test_mfma_probe_rate():
+    """The attainable FP32 MFMA rate: positive, at most the published peak
+    (157.3 TFLOP/s, with a margin for timing), and well above what a
+    one-wave-per-SIMD latency-bound loop would show."""
+    t = ddpinn.mfma_probe(2000)
+    _say(f"mfma probe {t:.1f} TFLOP/s")
+    assert 60.0 < t < 165.0
