@@ -344,18 +344,26 @@ def adam_step(theta, m, v, g, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta, m, v
 
 
-def train(prob, params, n_steps, round_to_f32=False):
-    """n_steps of (loss_and_grad, Adam) per subdomain; returns params and loss history."""
+def train(prob, params, n_steps, round_to_f32=False, state=None, return_state=False):
+    """n_steps of (loss_and_grad, Adam) per subdomain; returns params and loss
+    history (and the Adam state (m, v, t) with return_state).  state resumes
+    from an Adam state returned earlier."""
     ps = [np.asarray(p, np.float64) for p in params]
-    ms = [np.zeros_like(p) for p in ps]
-    vs = [np.zeros_like(p) for p in ps]
+    if state is None:
+        ms = [np.zeros_like(p) for p in ps]
+        vs = [np.zeros_like(p) for p in ps]
+        t0 = 0
+    else:
+        ms, vs, t0 = [m.copy() for m in state[0]], [v.copy() for v in state[1]], state[2]
     hist = []
-    for t in range(1, n_steps + 1):
+    for t in range(t0 + 1, t0 + n_steps + 1):
         feed = [p.astype(np.float32) for p in ps] if round_to_f32 else ps
         terms, grads = loss_and_grad(prob, feed)
         hist.append(terms)
         for q in range(prob.n_sd):
             ps[q], ms[q], vs[q] = adam_step(ps[q], ms[q], vs[q], grads[q], t, prob.subdomains[q].lr)
+    if return_state:
+        return ps, np.stack(hist), (ms, vs, t0 + n_steps)
     return ps, np.stack(hist)
 
 

@@ -769,3 +769,16 @@ def test_table4_inverse_problem_inputs_and_gradient():
         np.testing.assert_allclose(grads[q][idx], fd[idx], rtol=2e-6, atol=1e-7 * np.abs(grads[q]).max())
         for lhs, rhs in _slope_identity(None, params[q].astype(np.float64), grads[q], [sd.widths, sd.aux_widths]):
             assert lhs == pytest.approx(rhs, rel=1e-10, abs=1e-14)
+
+
+def test_oracle_training_resumes_exactly():
+    """Oracle Adam: 3 steps, then 2 more from the returned state, equal 5
+    straight steps exactly."""
+    prob = _two_box("xpinn", n_res=12)
+    p0 = [s.params for s in prob.subdomains]
+    ps5, h5 = O.train(prob, p0, 5)
+    ps3, h3, st = O.train(prob, p0, 3, return_state=True)
+    ps2, h2 = O.train(prob, ps3, 2, state=st)
+    for a, b in zip(ps5, ps2):
+        assert np.array_equal(a, b)
+    assert np.array_equal(h5, np.concatenate([h3, h2]))
