@@ -116,8 +116,8 @@ def main():
                     help="report another workload (the benchmark line is the 16-subdomain XPINN Poisson one)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs "
-              f"all subdomains on a single GPU)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs "
+              f"all subdomains of a problem on one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
