@@ -137,7 +137,7 @@ def main():
     if args.kernel_only:
         pb = ddpinn.Problem(prob, fused=True, device="cuda:0", chunk_points=args.chunk_points)
         if not args.no_autotune:
-            pb.autotune(iters=10, cache_path=args.autotune_cache)
+            pb.autotune(iters=20, cache_path=args.autotune_cache)
         pb.step(2)
         kt = pb.time_kernels(args.kernel_only)
         pb.close()
@@ -155,7 +155,7 @@ def main():
         if not args.no_autotune:
             # work-plan choice (points per item, items per workgroup, workgroups
             # per CU) by the library's autotuner; set-up, outside the timed steps
-            plan = pb.autotune(iters=10, cache_path=args.autotune_cache)
+            plan = pb.autotune(iters=20, cache_path=args.autotune_cache)
         pb.plan = plan
         pb.step(args.warmup)
         torch.cuda.synchronize()

@@ -605,3 +605,16 @@ def test_mfma_probe_rate():
     t = ddpinn.mfma_probe(2000)
     _say(f"mfma probe {t:.1f} TFLOP/s")
     assert 60.0 < t < 165.0
+
+
+def test_cpinn_burgers_time_interfaces():
+    """cPINN across space and time interfaces of 2 x 3 space-time boxes: the
+    time component u of the space-time flux and its adjoint."""
+    prob = W.burgers_space_time("cpinn", 2, 3, seed=4, scale=0.05)
+    assert any(tuple(e.normal) == (0.0, 1.0) for e in prob.interfaces)
+    params = _params(prob, 17)
+    _say("cpinn burgers with time interfaces")
+    for fused in (True, False):
+        pb, lt, g = run(prob, params, fused=fused)
+        compare(prob, params, lt, g)
+        pb.close()
