@@ -25,7 +25,8 @@
  *    stream-ordered on the stream given to ddp_finalize and returns without
  *    waiting; ddp_sync() waits and reports non-finite losses.
  *  - Parameters of one network use the canonical flat layout: for each layer
- *    k = 1..L, W^k as [N_k][N_{k-1}] row-major followed by b^k[N_k].
+ *    k = 1..L, W^k as [N_k][N_{k-1}] row-major followed by b^k[N_k]; an
+ *    adaptive network (ddp_set_activation) then has its slopes a^1..a^{L-1}.
  *  - A handle is not thread-safe; use one handle per thread.
  */
 #ifndef DDPINN_H
