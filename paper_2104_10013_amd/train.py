@@ -41,9 +41,17 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--report-every", type=int, default=0, help="0: only at the end")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--lr", type=float, default=None, help="Adam learning rate of every subdomain (default: the workload's)")
+    ap.add_argument("--loss-w", type=float, nargs=4, default=None, metavar=("W_U", "W_F", "W_I", "W_4"),
+                    help="loss weights of every subdomain (data, residual, average, flux or residual continuity)")
     args = ap.parse_args(argv)
 
     prob = W.make_problem(args.workload, seed=args.seed, scale=args.scale)
+    for sd in prob.subdomains:
+        if args.lr is not None:
+            sd.lr = args.lr
+        if args.loss_w is not None:
+            sd.loss_w = tuple(args.loss_w)
     pb = ddpinn.Problem(prob, fused=True)
     if not args.no_autotune:
         pb.autotune(iters=5)
@@ -63,6 +71,7 @@ def main(argv=None):
     secs = time.perf_counter() - t0
     final = stitched_errors(pb, prob)
     print(json.dumps({"workload": args.workload, "seed": args.seed, "scale": args.scale, "steps": args.steps,
+                      "lr": args.lr, "loss_w": args.loss_w,
                       "rel_l2_init": init, "rel_l2_final": final, "train_s": secs,
                       "steps_per_s": args.steps / secs}), flush=True)
     pb.close()

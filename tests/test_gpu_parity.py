@@ -618,3 +618,29 @@ def test_cpinn_burgers_time_interfaces():
         pb, lt, g = run(prob, params, fused=fused)
         compare(prob, params, lt, g)
         pb.close()
+
+
+def test_general_activation_kernels_match_plain_bitwise():
+    """A tanh problem runs in the plain kernels; the same problem with one
+    extra, unconnected sin subdomain runs in the general-activation kernels.
+    With one tile per work item (the same summation order), the tanh
+    subdomains' loss terms and gradients agree bit for bit."""
+    base = W.custom_box_problem("xpinn", "poisson2d", 2, 2,
+                                [[2, 20, 20, 1], [2, 48, 48, 48, 1], [2, 64, 64, 1], [2, 80, 80, 80, 1]],
+                                [130, 257, 64, 199], n_bnd_seg=9, n_iface=77, seed=21)
+    extra = W.custom_box_problem("xpinn", "poisson2d", 1, 1, [[2, 33, 33, 1]], [90], n_bnd_seg=5, n_iface=1,
+                                 seed=22, domain=(2.0, 3.0, 0.0, 1.0))
+    W.with_activations(extra, ("sin",))
+    mixed = W.custom_box_problem("xpinn", "poisson2d", 2, 2,
+                                 [[2, 20, 20, 1], [2, 48, 48, 48, 1], [2, 64, 64, 1], [2, 80, 80, 80, 1]],
+                                 [130, 257, 64, 199], n_bnd_seg=9, n_iface=77, seed=21)
+    mixed.subdomains.append(extra.subdomains[0])
+    params = _params(base, 23)
+    _say("general-activation kernels vs plain, bitwise")
+    pa, la, ga = run(base, params, chunk_points=64)
+    pb, lb, gb = run(mixed, params + [extra.subdomains[0].params], chunk_points=64)
+    assert np.array_equal(la, lb[:4])
+    for q in range(4):
+        assert np.array_equal(ga[q], gb[q])
+    pa.close()
+    pb.close()
