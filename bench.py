@@ -173,6 +173,8 @@ def main():
     print(f"# fused: {ms_fused:.4f} ms/step", file=sys.stderr, flush=True)
     kt = pf.time_kernels(max(10, min(args.steps, 50)))
     print(f"# kernels: {kt}", file=sys.stderr, flush=True)
+    phases = pf.time_phases(max(10, min(args.steps, 50)))
+    print(f"# phases: {phases}", file=sys.stderr, flush=True)
     pf.close()
     plain = None
     if not args.no_plain:
@@ -205,6 +207,7 @@ def main():
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_fused) if plain else None,
         "kernel_ms": kt,
+        "phases_ms": phases,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

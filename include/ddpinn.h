@@ -206,6 +206,17 @@ int ddp_sync(ddp_problem* p);
  * Leaves parameters and the Adam state unchanged. */
 int ddp_time_kernels(ddp_problem* p, int iters, float* ms);
 
+/* Phase timing of the fused step (cf. Fig. 4's data-loss / residual-loss
+ * split): mean milliseconds over iters runs of the step's train launches
+ * restricted to the work items of one phase, ms[0] residual points, ms[1]
+ * training (data) points, ms[2] interface points, ms[3] all items.  The
+ * phases' sum exceeds ms[3] by what their separate launches do not overlap.
+ * Synchronous; allocates and frees a device copy of the item list.  Leaves
+ * parameters and the Adam state unchanged.  DDP_ESTATE for the per-subdomain
+ * path or before ddp_finalize; DDP_EINVAL for iters < 1 or a null ms (4
+ * floats). */
+int ddp_time_phases(ddp_problem* p, int iters, float* ms);
+
 /* Measurement: the FP32 matrix-core rate the current device sustains, in
  * TFLOP/s, on a loop of 16x16x4 FP32 MFMAs with no memory traffic (eight
  * waves per SIMD, iters unrolled steps of four independent MFMAs per wave;

@@ -1188,6 +1188,64 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
   return DDP_OK;
 }
 
+int ddp_time_phases(ddp_problem* p, int iters, float* ms) {
+  if (int rc = check_final(p)) return rc;
+  if (iters < 1 || !ms) return fail(DDP_EINVAL, "bad timing arguments");
+  if (!p->fused) return fail(DDP_ESTATE, "phase timing is for the fused step");
+  // the step's launches restricted to the items of one phase, in the step's order
+  const int kinds[4] = {1 << KIND_RES, (1 << KIND_DATA) | (1 << KIND_AUX), 1 << KIND_IFACE,
+                        (1 << KIND_RES) | (1 << KIND_DATA) | (1 << KIND_AUX) | (1 << KIND_IFACE)};
+  Item* d_sel = nullptr;
+  HIP_TRY(hipMalloc(&d_sel, std::max<size_t>(1, p->titems.size()) * sizeof(Item)));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int rc = DDP_OK;
+  auto hip_ok = [&](hipError_t e) {
+    if (e != hipSuccess && rc == DDP_OK) rc = fail(DDP_EHIP, hipGetErrorString(e));
+    return rc == DDP_OK;
+  };
+  if (hip_ok(hipEventCreate(&ev[0])) && hip_ok(hipEventCreate(&ev[1]))) {
+    for (int ph = 0; ph < 4 && rc == DDP_OK; ++ph) {
+      std::vector<Item> sel;
+      std::vector<int> begin, count;
+      for (const ddp_problem::Launch& l : p->launches) {
+        begin.push_back((int)sel.size());
+        for (int i = l.begin; i < l.begin + l.count; ++i)
+          if (kinds[ph] & (1 << p->titems[i].kind)) sel.push_back(p->titems[i]);
+        count.push_back((int)sel.size() - begin.back());
+      }
+      if (!sel.empty() && !hip_ok(hipMemcpy(d_sel, sel.data(), sel.size() * sizeof(Item), hipMemcpyHostToDevice)))
+        break;
+      float total = 0.f;
+      for (int it = 0; it < iters && rc == DDP_OK; ++it) {
+        for (int c = 0; c < p->n_counters && rc == DDP_OK; ++c)
+          hip_ok(launch_reset_counter(p->d_counters + c, p->stream));
+        if (!hip_ok(hipEventRecord(ev[0], p->stream))) break;
+        for (size_t g = 0; g < p->launches.size() && rc == DDP_OK; ++g) {
+          if (count[g] == 0) continue;
+          const ddp_problem::Launch& l = p->launches[g];
+          KArgs ka = make_kargs(p);
+          ka.items = d_sel + begin[g];
+          ka.n_items = count[g];
+          ka.counter = p->d_counters + g;
+          ka.scratch_slot = l.slot_floats;
+          hip_ok(launch_train(p->pde, l.wpmax, p->ga, ka, std::max(1, std::min(l.n_slots, count[g])), p->stream));
+        }
+        float t = 0.f;
+        if (hip_ok(hipEventRecord(ev[1], p->stream)) && hip_ok(hipEventSynchronize(ev[1])) &&
+            hip_ok(hipEventElapsedTime(&t, ev[0], ev[1])))
+          total += t;
+      }
+      ms[ph] = total / iters;
+    }
+  }
+  for (int c = 0; c < p->n_counters; ++c) hip_ok(launch_reset_counter(p->d_counters + c, p->stream));
+  hip_ok(hipStreamSynchronize(p->stream));
+  if (ev[0]) hipEventDestroy(ev[0]);
+  if (ev[1]) hipEventDestroy(ev[1]);
+  hipFree(d_sel);
+  return rc;
+}
+
 int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   if (!p || !json_path) return fail(DDP_EINVAL, "null argument");
   if (!p->planned) return fail(DDP_ESTATE, "no plan: call ddp_plan or ddp_finalize first");

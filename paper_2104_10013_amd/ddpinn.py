@@ -32,6 +32,7 @@ EXPORTED = [
     "ddp_finalize", "ddp_param_count", "ddp_set_params", "ddp_get_params", "ddp_loss_and_grad",
     "ddp_step", "ddp_get_state", "ddp_set_state", "ddp_eval", "ddp_sync", "ddp_time_kernels",
     "ddp_plan_dump", "ddp_plan", "ddp_last_error", "ddp_destroy", "ddp_autotune", "ddp_mfma_probe",
+    "ddp_time_phases",
 ]
 
 _METHOD = {W.METHOD_CPINN: DDP_CPINN, W.METHOD_XPINN: DDP_XPINN}
@@ -82,6 +83,7 @@ def load_library(path=LIB_PATH):
         "ddp_destroy": ([P], I),
         "ddp_autotune": ([P, I, ctypes.c_char_p, pI64], I),
         "ddp_mfma_probe": ([I, ctypes.POINTER(D)], I),
+        "ddp_time_phases": ([P, I, pF], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -257,6 +259,13 @@ class Problem:
         ms = (ctypes.c_float * 2)()
         _check(_lib.ddp_time_kernels(self._h, int(iters), ms))
         return {"train_ms": ms[0], "reduce_ms": ms[1]}
+
+    def time_phases(self, iters=10):
+        """Mean ms of the fused step's train launches per phase: residual,
+        data and interface items, and all items."""
+        ms = (ctypes.c_float * 4)()
+        _check(_lib.ddp_time_phases(self._h, int(iters), ms))
+        return {"residual_ms": ms[0], "data_ms": ms[1], "interface_ms": ms[2], "all_ms": ms[3]}
 
     def autotune(self, iters=5, cache_path=None):
         """Pick the fastest work plan (see ddp_autotune); returns the choice."""

@@ -193,6 +193,8 @@ def test_input_validation_codes():
     assert L.ddp_param_count(h, 1, ct.byref(n)) == 0 and n.value == W.param_count([2, 8, 8, 1])
     assert L.ddp_set_option(h, 99, 1) == ddpinn.DDP_EINVAL
     # calls that need a finalized problem
+    ms4 = (ct.c_float * 4)()
+    assert L.ddp_time_phases(h, 5, ms4) == ddpinn.DDP_ESTATE
     assert L.ddp_step(h, 1, None) == ddpinn.DDP_ESTATE
     assert L.ddp_sync(h) == ddpinn.DDP_ESTATE
     assert L.ddp_plan_dump(h, b"/tmp/x.json") == ddpinn.DDP_ESTATE

@@ -644,3 +644,23 @@ def test_general_activation_kernels_match_plain_bitwise():
         assert np.array_equal(ga[q], gb[q])
     pa.close()
     pb.close()
+
+
+def test_phase_timing_of_the_fused_step():
+    """Train time split by point kind on the 16-subdomain problem: residual
+    items dominate, every phase is timed, and the phases add up to at least
+    the whole launch (their separate launches cannot overlap)."""
+    prob = W.c2_xpinn_poisson(seed=0, scale=0.3)
+    pb = ddpinn.Problem(prob, fused=True)
+    pb.step(2)
+    ph = pb.time_phases(5)
+    kt = pb.time_kernels(5)
+    _say(f"phases {ph} kernels {kt}")
+    assert ph["residual_ms"] > ph["interface_ms"] > 0 and ph["data_ms"] > 0
+    assert ph["residual_ms"] + ph["interface_ms"] + ph["data_ms"] >= 0.9 * ph["all_ms"]
+    assert 0.5 * kt["train_ms"] < ph["all_ms"] < 2.0 * kt["train_ms"]
+    pl = ddpinn.Problem(prob, fused=False)
+    with pytest.raises(ddpinn.DDPError):
+        pl.time_phases(1)
+    pl.close()
+    pb.close()
