@@ -650,7 +650,7 @@ def test_phase_timing_of_the_fused_step():
     """Train time split by point kind on the 16-subdomain problem: residual
     items dominate, every phase is timed, and the phases add up to at least
     the whole launch (their separate launches cannot overlap)."""
-    prob = W.c2_xpinn_poisson(seed=0, scale=0.3)
+    prob = W.c2_xpinn_poisson(seed=0)
     pb = ddpinn.Problem(prob, fused=True)
     pb.step(2)
     ph = pb.time_phases(5)
