@@ -142,6 +142,27 @@ __device__ __forceinline__ void tanh_adj(float a, float ax, float ay, float al, 
   ab = fmaf(s1, g, fmaf(s2, fmaf(ax, gx, ay * gy), fmaf(s2, al, s3 * q) * gl));
 }
 
+// sin and cos of y: quadrant q = rint(2y/pi), r = y - q pi/2 in three parts
+// (Cody and Waite; the first part has 8 significant bits, so q x part is exact
+// for |q| < 2^16, i.e. |y| below about 1e5), then the minimax polynomials of
+// the Cephes single-precision sinf / cosf on [-pi/4, pi/4] (about 1e-7
+// relative).  Register-light where pre-activations are small.
+__device__ __forceinline__ void sin_cos(float y, float& sn, float& cs) {
+  const float q = rintf(y * 0.636619772367581343f);
+  float r = fmaf(-q, 1.5703125f, y);
+  r = fmaf(-q, 4.837512969970703125e-4f, r);
+  r = fmaf(-q, 7.54978995489188216e-8f, r);
+  const float r2 = r * r;
+  const float ps = fmaf(fmaf(-1.9515295891e-4f, r2, 8.3321608736e-3f), r2, -1.6666654611e-1f);
+  const float s0 = fmaf(ps * r2, r, r);
+  const float pc = fmaf(fmaf(2.443315711809948e-5f, r2, -1.388731625493765e-3f), r2, 4.166664568298827e-2f);
+  const float c0 = fmaf(pc * r2, r2, fmaf(-0.5f, r2, 1.f));
+  const int iq = (int)q & 3;
+  const float a = (iq & 1) ? c0 : s0, b = (iq & 1) ? s0 : c0;
+  sn = (iq & 2) ? -a : a;
+  cs = ((iq + 1) & 2) ? -b : b;
+}
+
 // General activation (Sec. 3): h = Phi(c a) with the effective slope c = n a^k
 // of the layer and Phi in {tanh, sin, cos}.  The Taylor streams of y = c a are
 // c times those of a, so the rule is the unit-slope one on the scaled streams:
@@ -157,7 +178,7 @@ __device__ __forceinline__ void act_derivs(int act, float y, float& f0, float& f
     f3 = -2.f * s1 * (1.f - 3.f * t * t);
   } else {
     float sn, cs;
-    sincosf(y, &sn, &cs);
+    sin_cos(y, sn, cs);
     f0 = act == ACT_SIN ? sn : cs;
     f1 = act == ACT_SIN ? cs : -sn;
     f2 = -f0;
