@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-phases", action="store_true",
+                    help="skip the per-phase timing (whose launches would join a kernel trace)")
     ap.add_argument("--chunk-points", type=int, default=None)
     ap.add_argument("--no-autotune", action="store_true", help="time the default work plan")
     ap.add_argument("--autotune-cache", default=None, metavar="PATH",
@@ -173,7 +175,7 @@ def main():
     print(f"# fused: {ms_fused:.4f} ms/step", file=sys.stderr, flush=True)
     kt = pf.time_kernels(max(10, min(args.steps, 50)))
     print(f"# kernels: {kt}", file=sys.stderr, flush=True)
-    phases = pf.time_phases(max(10, min(args.steps, 50)))
+    phases = None if args.no_phases else pf.time_phases(max(10, min(args.steps, 50)))
     print(f"# phases: {phases}", file=sys.stderr, flush=True)
     pf.close()
     plain = None
