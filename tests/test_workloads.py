@@ -1,6 +1,9 @@
 """Host checks of the space-time Burgers inputs (Sec. 7.5, Table 3): every
 point lies where its role says, the counts add up to the paper's totals, and
 every subdomain / interface is present once."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -67,3 +70,48 @@ def test_space_time_burgers_is_seeded():
     assert all(np.array_equal(s.res_xy, t.res_xy) and np.array_equal(s.params, t.params)
                for s, t in zip(a.subdomains, b.subdomains))
     assert not np.array_equal(a.subdomains[0].res_xy, c.subdomains[0].res_xy)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    """A configuration the paper prints, transcribed with its citation."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def test_table4_setup_matches_the_paper():
+    """The generator's Table 4 workload against the table as printed."""
+    g = _golden("table4_networks.json")
+    prob = W.c5_table4_adaptive(seed=0)
+    assert [s.res_xy.shape[0] for s in prob.subdomains] == g["residual_points"]
+    assert [s.act for s in prob.subdomains] == g["activation"]
+    hidden = [g["neurons_per_layer"]] * g["hidden_layers"]
+    for s in prob.subdomains:
+        assert s.widths == [2] + hidden + [1] and s.aux_widths == [2] + hidden + [1]
+        assert s.lr == pytest.approx(g["learning_rate"]) and s.adaptive
+
+
+def test_table3_setup_matches_the_paper():
+    """The space-time Burgers partitions and network set-up of Table 3."""
+    g = _golden("table3_partitions.json")
+    parts = [("cpinn", nx, nt) for nx, nt in g["cpinn_x_t_partitions"]] + \
+            [("xpinn", nx, nt) for nx, nt in g["xpinn_x_t_partitions"]]
+    assert tuple(parts) == W.TABLE3_PARTITIONS
+    for method, nx, nt in parts:
+        prob = W.make_problem(f"burgers_st_{method}_{nx}x{nt}", seed=0)
+        assert abs(prob.n_residual() - g["residual_points_whole_domain"]) <= nx * nt
+        assert all(len(e.xy) == g["interface_points"] for e in prob.interfaces)
+        for s in prob.subdomains:
+            assert s.widths == [2] + [g["neurons_per_layer"]] * g["hidden_layers"] + [1]
+            assert s.lr == pytest.approx(g["learning_rate"])
+        assert prob.coef[0] == pytest.approx(0.01 / np.pi)
+    # initial data on the first time slab: u(0, x) = -sin(pi x); walls u = 0 at x = -1, 1
+    prob = W.make_problem("burgers_st_xpinn_4x2", seed=0)
+    for s in prob.subdomains:
+        b, v = s.bnd_xy.astype(np.float64), s.bnd_g[:, 0].astype(np.float64)
+        ic = b[:, 1] == g["domain"]["t_from"]
+        np.testing.assert_allclose(v[ic], -np.sin(np.pi * b[ic, 0]), atol=1e-6)
+        wall = np.isin(b[:, 0], g["domain"]["x"]) & ~ic
+        assert np.all(v[wall] == 0)
