@@ -664,3 +664,22 @@ def test_phase_timing_of_the_fused_step():
         pl.time_phases(1)
     pl.close()
     pb.close()
+
+
+def test_many_subdomains_random_widths_and_depths():
+    """64 subdomains (8 x 8, XPINN Poisson) with a random width from 16 to 112
+    and 1-6 hidden layers each, ragged residual counts (some empty) and 1-90
+    points per interface: both width-class launches, both paths."""
+    rng = np.random.default_rng(31)
+    widths = [[2] + [int(rng.integers(16, 113))] * int(rng.integers(1, 7)) + [1] for _ in range(64)]
+    counts = [int(c) if c > 20 else 0 for c in rng.integers(0, 400, 64)]
+    prob = W.custom_box_problem("xpinn", "poisson2d", 8, 8, widths, counts, n_bnd_seg=6, n_iface=90, seed=32)
+    for e in prob.interfaces:
+        e.xy = e.xy[: int(rng.integers(1, 91))].copy()
+    params = _params(prob, 33)
+    for fused in (True, False):
+        _say(f"64 random subdomains fused {fused}")
+        pb, lt, g = run(prob, params, fused=fused)
+        wl, wg = compare(prob, params, lt, g)
+        _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+        pb.close()
