@@ -782,3 +782,80 @@ def test_oracle_training_resumes_exactly():
     for a, b in zip(ps5, ps2):
         assert np.array_equal(a, b)
     assert np.array_equal(h5, np.concatenate([h3, h2]))
+
+
+# --------------------------------------------------------------------------
+# relative L2 error of the stitched solution, and the oracle's training loop
+
+
+def test_rel_l2_hand_built_vectors():
+    """||u - u*|| / ||u*|| on vectors whose ratio is known by construction:
+    a scaled copy, an orthogonal perturbation (a Pythagorean triple), and a
+    multi-column array taken as one vector (Frobenius norm)."""
+    ue = np.array([3.0, 4.0])                      # ||u*|| = 5
+    assert O.rel_l2(ue, ue) == 0.0
+    assert O.rel_l2(1.2 * ue, ue) == pytest.approx(0.2, rel=1e-15)
+    assert O.rel_l2(-ue, ue) == pytest.approx(2.0, rel=1e-15)
+    # perturbation (-4, 3) is orthogonal to u* with norm 5: ratio exactly 1,
+    # while ||u|| / ||u*|| - 1 would give sqrt(2) - 1
+    assert O.rel_l2(ue + np.array([-4.0, 3.0]), ue) == pytest.approx(1.0, rel=1e-15)
+    # two columns (u, K): the error is over all entries together
+    ue2 = np.array([[1.0, 2.0], [2.0, 4.0]])       # ||u*||_F = 5
+    d = np.array([[0.0, 1.0], [0.0, 0.0]])
+    assert O.rel_l2(ue2 + d, ue2) == pytest.approx(0.2, rel=1e-15)
+    # per-column errors would differ (0 and 1/sqrt(20)); the whole-array value does not
+    assert O.rel_l2((ue2 + d)[:, 0], ue2[:, 0]) == 0.0
+
+
+def test_oracle_train_matches_torch_adam_per_subdomain():
+    """The oracle's training loop against torch.optim.Adam, one optimiser per
+    subdomain with that subdomain's learning rate, fed the oracle's gradient at
+    the current parameters: steps t = 1, 2, 3 straight, then a resume from the
+    returned state (t0 = 3) for two more.  An offset in the step index t of
+    the bias correction, a shared learning rate or a history entry taken after
+    the update fails it."""
+    prob = _two_box("xpinn", n_res=12)
+    prob.subdomains[0].lr = 2e-2
+    prob.subdomains[1].lr = 5e-3
+    p0 = [s.params.astype(np.float64) for s in prob.subdomains]
+    tp = [torch.tensor(p.copy(), dtype=DT, requires_grad=True) for p in p0]
+    opts = [torch.optim.Adam([t], lr=s.lr, betas=(0.9, 0.999), eps=1e-8) for t, s in zip(tp, prob.subdomains)]
+    ref_hist = []
+    ref_params = []
+    for step in range(5):
+        cur = [t.detach().numpy().copy() for t in tp]
+        terms, grads = O.loss_and_grad(prob, cur)
+        ref_hist.append(terms)
+        for q in range(2):
+            tp[q].grad = torch.tensor(grads[q], dtype=DT)
+            opts[q].step()
+        ref_params.append([t.detach().numpy().copy() for t in tp])
+    ps3, h3, st = O.train(prob, p0, 3, return_state=True)
+    assert st[2] == 3
+    for q in range(2):
+        np.testing.assert_allclose(ps3[q], ref_params[2][q], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(h3, np.stack(ref_hist[:3]), rtol=1e-12, atol=1e-15)
+    ps5, h2, st5 = O.train(prob, ps3, 2, state=st, return_state=True)
+    assert st5[2] == 5
+    for q in range(2):
+        np.testing.assert_allclose(ps5[q], ref_params[4][q], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(h2, np.stack(ref_hist[3:]), rtol=1e-12, atol=1e-15)
+    # the steps really moved the parameters by more than the tolerance
+    assert min(np.abs(ps5[q] - p0[q]).max() for q in range(2)) > 1e-4
+
+
+def test_oracle_train_step_index_offset_is_detected():
+    """Planted mistake (on the CPU): an Adam loop whose bias correction uses
+    t + 1 instead of t departs from torch.optim.Adam at the tolerance of the
+    test above, so that test would catch it."""
+    rng = np.random.default_rng(3)
+    th0 = rng.normal(size=25)
+    gs = [rng.normal(size=25) for _ in range(3)]
+    p = torch.tensor(th0.copy(), dtype=DT, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    th, m, v = th0.copy(), np.zeros(25), np.zeros(25)
+    for t, g in enumerate(gs, start=1):
+        p.grad = torch.tensor(g, dtype=DT)
+        opt.step()
+        th, m, v = O.adam_step(th, m, v, g, t + 1, 1e-2)
+    assert np.abs(th - p.detach().numpy()).max() > 1e-5
