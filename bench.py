@@ -70,9 +70,21 @@ def traffic_from_profile(n_launch_units):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(prob, reps=3):
     """The FP64 oracle (loss_and_grad + Adam of every subdomain) timed on the
-    host's cores; the sample is `reps` full steps of the same workload."""
+    host's cores; the sample is `reps` full steps of the same workload after
+    one warm-up step, with torch's thread pool as set up (OMP_NUM_THREADS),
+    then again on one thread (one warm-up, one timed step)."""
     import torch
     import oracle
     params = [s.params.astype(np.float64) for s in prob.subdomains]
@@ -84,16 +96,34 @@ def cpu_baseline(prob, reps=3):
         for q in range(prob.n_sd):
             oracle.adam_step(params[q], ms[q], vs[q], grads[q], t, prob.subdomains[q].lr)
 
+    def timed(n, t0):
+        times = []
+        for r in range(n):
+            a = time.perf_counter()
+            one_step(t0 + r)
+            times.append(time.perf_counter() - a)
+        return float(np.median(times))
+
+    threads = torch.get_num_threads()
     one_step(1)  # warm-up
-    times = []
-    for r in range(reps):
-        t0 = time.perf_counter()
-        one_step(r + 2)
-        times.append(time.perf_counter() - t0)
-    med = float(np.median(times))
-    return {"value": prob.n_residual() / med, "unit": "residual points/s", "cores": torch.get_num_threads(),
-            "kind": "oracle", "sample": f"{reps} full FP64 oracle steps (loss, gradient, Adam) of the same "
-                                        f"workload, median {med:.2f} s/step"}
+    med = timed(reps, 2)
+    torch.set_num_threads(1)
+    try:
+        one_step(reps + 2)  # warm-up on one thread
+        med1 = timed(1, reps + 3)
+    finally:
+        torch.set_num_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"value": prob.n_residual() / med, "unit": "residual points/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} full FP64 oracle steps (loss, gradient, Adam) of the same workload after one "
+                      f"warm-up, median {med:.2f} s/step on {threads} threads; then one warm-up and one "
+                      f"timed step on 1 thread, {med1:.2f} s/step",
+            "value_1thread": prob.n_residual() / med1, "cpu_model": cpu_model(),
+            "affinity_cores": affinity, "os_cpu_count": os.cpu_count()}
 
 
 def main():
@@ -102,6 +132,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", default="0,1,2",
+                    help="seeds whose fused step is also timed over --repeats windows (median reported); "
+                         "the headline value is --seed's single window")
+    ap.add_argument("--repeats", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-phases", action="store_true",
@@ -151,22 +185,29 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
 
-    def time_path(fused):
-        pb = ddpinn.Problem(prob, fused=fused, device=dev, stream=stream, chunk_points=args.chunk_points)
+    def make(problem, fused):
+        pb = ddpinn.Problem(problem, fused=fused, device=dev, stream=stream, chunk_points=args.chunk_points)
         plan = None
         if not args.no_autotune:
             # work-plan choice (points per item, items per workgroup, workgroups
             # per CU) by the library's autotuner; set-up, outside the timed steps
             plan = pb.autotune(iters=20, cache_path=args.autotune_cache)
         pb.plan = plan
-        pb.step(args.warmup)
+        return pb
+
+    def window(pb, n):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        pb.step(args.steps)
+        pb.step(n)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
+        return e0.elapsed_time(e1) / n
+
+    def time_path(fused):
+        pb = make(prob, fused)
+        pb.step(args.warmup)
+        ms = window(pb, args.steps)
         pb.sync()
         return pb, ms
 
@@ -186,6 +227,28 @@ def main():
                  "steps_per_s": 1e3 / ms_plain, "plan": pp.plan}
         print(f"# plain: {ms_plain:.4f} ms/step", file=sys.stderr, flush=True)
 
+    # the fused step of each seed over `repeats` windows of `steps` steps
+    # (outside the headline window above): median ms per step
+    seeds = {}
+    if args.workload == WORKLOAD and args.seeds:
+        for sd in [int(x) for x in args.seeds.split(",") if x.strip()]:
+            pr = prob if sd == args.seed else W.make_problem(args.workload, seed=sd)
+            pb = make(pr, True)
+            pb.step(args.warmup)
+            wins = [window(pb, args.steps) for _ in range(args.repeats)]
+            pb.sync()
+            kts = pb.time_kernels(max(10, min(args.steps, 50)))
+            pb.close()
+            med = float(np.median(wins))
+            f_sd = algorithmic_flops(pr)
+            seeds[str(sd)] = {"n_residual": pr.n_residual(), "ms_per_step_median": med,
+                              "ms_per_step_windows": wins, "value_median": pr.n_residual() / (med * 1e-3),
+                              "train_ms": kts["train_ms"],
+                              "frac": f_sd / (kts["train_ms"] * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                              "step_frac": f_sd / (med * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS}
+            print(f"# seed {sd}: median {med:.4f} ms/step over {args.repeats} windows, train "
+                  f"{kts['train_ms']:.4f} ms", file=sys.stderr, flush=True)
+
     achieved = flops / (kt["train_ms"] * 1e-3) / 1e12
     # the rate a pure MFMA loop sustains on this device (the part clocks below
     # its rated 2.4 GHz under full matrix load): the attainable peak
@@ -195,7 +258,10 @@ def main():
             "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
             "mfma_probe": probe, "frac_of_probe": achieved / probe if probe > 0 else None,
             "traffic": traffic_from_profile(1) if args.workload == WORKLOAD else None,
-            "kernel": "k_train", "kernel_ms": kt["train_ms"], "algorithmic_flop_per_launch": flops}
+            "kernel": "k_train", "kernel_ms": kt["train_ms"], "algorithmic_flop_per_launch": flops,
+            # the whole step (train and reduce/Adam kernels, as ms_per_step)
+            "step_achieved": flops / (ms_fused * 1e-3) / 1e12,
+            "step_frac": flops / (ms_fused * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS}
     out = {
         "metric": METRIC, "value": n_res / (ms_fused * 1e-3), "unit": "residual points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_fused, "higher_is_better": True,
@@ -210,6 +276,7 @@ def main():
         "speedup_vs_plain": (plain["ms_per_step"] / ms_fused) if plain else None,
         "kernel_ms": kt,
         "phases_ms": phases,
+        "seeds": seeds or None,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

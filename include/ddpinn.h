@@ -125,6 +125,8 @@ int ddp_add_interface(ddp_problem* p, int sd_a, int sd_b, int n, const float* xy
  * network's layers in the canonical flat layout (so ddp_param_count grows by
  * D per network), their gradients are dJ/da^k, Adam updates them, and the
  * paper initialises them to n a^k = 1.  adaptive = 0 fixes n a^k = 1.
+ * sin and cos are evaluated to about 1e-7 absolute for |n a^k x| up to 1e5;
+ * larger arguments lose accuracy (there is no check on the device).
  * DDP_EINVAL for an unknown subdomain or activation, adaptive not 0/1, or
  * slope_n not finite and > 0.  Valid before ddp_finalize. */
 int ddp_set_activation(ddp_problem* p, int sd, int act, int adaptive, float slope_n);

@@ -85,6 +85,7 @@ struct ddp_problem {
 
   // plan
   bool planned = false, finalized = false;
+  bool plan_ok = false;          // install_plan completed: work list, rows, stash and graph are in place
   int fused = 1;
   int wpmax = 16;                // width group of the (plain path's) train kernel
   bool ga = false;               // some network needs the general activation rule
@@ -588,6 +589,7 @@ int check_open(const ddp_problem* p) {
 int check_final(const ddp_problem* p) {
   if (!p) return fail(DDP_EINVAL, "null problem handle");
   if (!p->finalized) return fail(DDP_ESTATE, "call ddp_finalize first");
+  if (!p->plan_ok) return fail(DDP_ESTATE, "no work plan is installed (a failed re-plan could not restore it)");
   return DDP_OK;
 }
 
@@ -786,6 +788,7 @@ namespace {
 // activation stash, work counters and the step graph.
 int install_plan(ddp_problem* p) {
   const int n_sd = (int)p->sds.size();
+  p->plan_ok = false;
   if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
   if (p->graph) hipGraphDestroy(p->graph);
   p->graph_exec = nullptr;
@@ -838,6 +841,7 @@ int install_plan(ddp_problem* p) {
     p->graph = g;
     HIP_TRY(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
   }
+  p->plan_ok = true;
   return DDP_OK;
 }
 
@@ -936,73 +940,99 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   return DDP_OK;
 }
 
+namespace {
+
+// The autotuner's search: every candidate plan timed over iters passes, the
+// three fastest again over three interleaved rounds; best receives the
+// winner.  Leaves the last candidate installed.
+int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, float* best_ms) {
+  int max_occ = p->occupancy;   // the fused launches may run narrower kernels
+  for (const ddp_problem::Launch& l : p->launches) max_occ = std::max(max_occ, l.occupancy);
+  const int64_t chunks[] = {256, 512, 1024, 2048};
+  const int ipss[] = {1, 2, 4, 8};
+  struct Cand {
+    int64_t c;
+    int ips, bpc;
+    float ms;
+  };
+  std::vector<Cand> cands;
+  // mean time of one loss + gradient pass (no Adam) of candidate k over n
+  // passes, after one untimed pass
+  auto time_cand = [&](const Cand& k, int n, float* ms) -> int {
+    p->chunk_points = k.c;
+    p->items_per_slot = k.ips;
+    p->blocks_per_cu = k.bpc;
+    if (int rc = install_plan(p)) return rc;
+    if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
+    HIP_TRY(hipEventRecord(ev[0], p->stream));
+    for (int i = 0; i < n; ++i)
+      if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
+    HIP_TRY(hipEventRecord(ev[1], p->stream));
+    HIP_TRY(hipEventSynchronize(ev[1]));
+    HIP_TRY(hipEventElapsedTime(ms, ev[0], ev[1]));
+    *ms /= n;
+    return DDP_OK;
+  };
+  for (int64_t c : chunks)
+    for (int ips : ipss)
+      for (int bpc = 1; bpc <= max_occ; ++bpc) {
+        Cand k{c, ips, bpc, 0.f};
+        if (int rc = time_cand(k, iters, &k.ms)) return rc;
+        cands.push_back(k);
+      }
+  // the leading candidates are often within a percent of each other: time the
+  // best three again, interleaved over three rounds of 2 x iters passes, and
+  // keep the smallest total
+  std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+  const int n_final = std::min<int>(3, (int)cands.size());
+  std::vector<float> total(n_final, 0.f);
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < n_final; ++k) {
+      float ms = 0.f;
+      if (int rc = time_cand(cands[k], 2 * iters, &ms)) return rc;
+      total[k] += ms;
+    }
+  *best_ms = 1e30f;
+  for (int k = 0; k < n_final; ++k)
+    if (total[k] / 3 < *best_ms) {
+      *best_ms = total[k] / 3;
+      best[0] = cands[k].c;
+      best[1] = cands[k].ips;
+      best[2] = cands[k].bpc;
+    }
+  return DDP_OK;
+}
+
+}  // namespace
+
 int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* choice) {
   if (int rc = check_final(p)) return rc;
   if (iters < 1) return fail(DDP_EINVAL, "iters must be >= 1");
   const uint64_t sig = problem_signature(p);
-  int64_t best[3] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu};
+  const int64_t prev[3] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu};
+  int64_t best[3] = {prev[0], prev[1], prev[2]};
+  // on any failure the previous plan is put back, so the handle stays usable;
+  // if even that fails, every later call reports DDP_ESTATE
+  auto restore = [&](int rc) {
+    const std::string msg = g_err;
+    p->chunk_points = prev[0];
+    p->items_per_slot = (int)prev[1];
+    p->blocks_per_cu = (int)prev[2];
+    install_plan(p);
+    g_err = msg;
+    return rc;
+  };
   if (!cache_lookup(cache_path, sig, best)) {
-    const int n_sd = (int)p->sds.size();
-    float best_ms = 1e30f;
-    hipEvent_t ev[2];
-    HIP_TRY(hipEventCreate(&ev[0]));
-    HIP_TRY(hipEventCreate(&ev[1]));
-    int max_occ = p->occupancy;   // the fused launches may run narrower kernels
-    for (const ddp_problem::Launch& l : p->launches) max_occ = std::max(max_occ, l.occupancy);
-    const int64_t chunks[] = {256, 512, 1024, 2048};
-    const int ipss[] = {1, 2, 4, 8};
-    struct Cand {
-      int64_t c;
-      int ips, bpc;
-      float ms;
-    };
-    std::vector<Cand> cands;
-    // mean time of one loss + gradient pass (no Adam) of candidate k over n
-    // passes, after one untimed pass
-    auto time_cand = [&](const Cand& k, int n, float* ms) -> int {
-      p->chunk_points = k.c;
-      p->items_per_slot = k.ips;
-      p->blocks_per_cu = k.bpc;
-      if (int rc = install_plan(p)) return rc;
-      if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
-      HIP_TRY(hipEventRecord(ev[0], p->stream));
-      for (int i = 0; i < n; ++i)
-        if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
-      HIP_TRY(hipEventRecord(ev[1], p->stream));
-      HIP_TRY(hipEventSynchronize(ev[1]));
-      HIP_TRY(hipEventElapsedTime(ms, ev[0], ev[1]));
-      *ms /= n;
-      return DDP_OK;
-    };
-    for (int64_t c : chunks)
-      for (int ips : ipss)
-        for (int bpc = 1; bpc <= max_occ; ++bpc) {
-          Cand k{c, ips, bpc, 0.f};
-          if (int rc = time_cand(k, iters, &k.ms)) return rc;
-          cands.push_back(k);
-        }
-    // the leading candidates are often within a percent of each other: time the
-    // best three again, interleaved over three rounds of 2 x iters passes, and
-    // keep the smallest total
-    std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
-    const int n_final = std::min<int>(3, (int)cands.size());
-    std::vector<float> total(n_final, 0.f);
-    for (int r = 0; r < 3; ++r)
-      for (int k = 0; k < n_final; ++k) {
-        float ms = 0.f;
-        if (int rc = time_cand(cands[k], 2 * iters, &ms)) return rc;
-        total[k] += ms;
-      }
-    for (int k = 0; k < n_final; ++k)
-      if (total[k] / 3 < best_ms) {
-        best_ms = total[k] / 3;
-        best[0] = cands[k].c;
-        best[1] = cands[k].ips;
-        best[2] = cands[k].bpc;
-      }
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
-    (void)n_sd;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    float best_ms = 0.f;
+    int rc = DDP_OK;
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) rc = fail(DDP_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    if (rc == DDP_OK) rc = autotune_search(p, iters, ev, best, &best_ms);
+    if (ev[0]) hipEventDestroy(ev[0]);
+    if (ev[1]) hipEventDestroy(ev[1]);
+    if (rc) return restore(rc);
     if (cache_path) {
       FILE* f = std::fopen(cache_path, "a");
       if (f) {
@@ -1017,7 +1047,7 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
   p->chunk_points = best[0];
   p->items_per_slot = (int)best[1];
   p->blocks_per_cu = (int)best[2];
-  if (int rc = install_plan(p)) return rc;
+  if (int rc = install_plan(p)) return restore(rc);
   if (choice) {
     choice[0] = best[0];
     choice[1] = best[1];

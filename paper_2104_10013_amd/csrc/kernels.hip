@@ -30,6 +30,7 @@
 
 #include <algorithm>
 
+#include "act_math.h"
 #include "ddp_internal.h"
 #include "kernels.h"
 
@@ -41,11 +42,6 @@ constexpr int TP = kTilePts;      // points per tile
 constexpr int TPS = kTilePts + 4; // LDS row stride of staged tiles (floats)
 constexpr int NT = 64 * kWaves;   // threads per workgroup
 
-// Wait until this wave's outstanding vector-memory stores have completed.
-// The stash and the partial rows are written and later re-read by the same
-// wave; the compiler orders those accesses only through registers, so every
-// re-read of stored data is preceded by this wait (and reads at device scope,
-// so no vector-L1 copy from before the store is used).
 // One 16-byte-per-lane store into the activation stash, followed by wait
 // states before anything may overwrite its data registers.  The compiler
 // treats a buffer store with an SGPR offset as free of the store-data
@@ -142,26 +138,8 @@ __device__ __forceinline__ void tanh_adj(float a, float ax, float ay, float al, 
   ab = fmaf(s1, g, fmaf(s2, fmaf(ax, gx, ay * gy), fmaf(s2, al, s3 * q) * gl));
 }
 
-// sin and cos of y: quadrant q = rint(2y/pi), r = y - q pi/2 in three parts
-// (Cody and Waite; the first part has 8 significant bits, so q x part is exact
-// for |q| < 2^16, i.e. |y| below about 1e5), then the minimax polynomials of
-// the Cephes single-precision sinf / cosf on [-pi/4, pi/4] (about 1e-7
-// relative).  Register-light where pre-activations are small.
-__device__ __forceinline__ void sin_cos(float y, float& sn, float& cs) {
-  const float q = rintf(y * 0.636619772367581343f);
-  float r = fmaf(-q, 1.5703125f, y);
-  r = fmaf(-q, 4.837512969970703125e-4f, r);
-  r = fmaf(-q, 7.54978995489188216e-8f, r);
-  const float r2 = r * r;
-  const float ps = fmaf(fmaf(-1.9515295891e-4f, r2, 8.3321608736e-3f), r2, -1.6666654611e-1f);
-  const float s0 = fmaf(ps * r2, r, r);
-  const float pc = fmaf(fmaf(2.443315711809948e-5f, r2, -1.388731625493765e-3f), r2, 4.166664568298827e-2f);
-  const float c0 = fmaf(pc * r2, r2, fmaf(-0.5f, r2, 1.f));
-  const int iq = (int)q & 3;
-  const float a = (iq & 1) ? c0 : s0, b = (iq & 1) ? s0 : c0;
-  sn = (iq & 2) ? -a : a;
-  cs = ((iq + 1) & 2) ? -b : b;
-}
+// sin_cos (act_math.h): Cody-Waite reduction and the Cephes single-precision
+// polynomials, register-light where pre-activations are small.
 
 // General activation (Sec. 3): h = Phi(c a) with the effective slope c = n a^k
 // of the layer and Phi in {tanh, sin, cos}.  The Taylor streams of y = c a are
@@ -1460,9 +1438,13 @@ __global__ __launch_bounds__(256) void k_eval(const float* params, const NetDesc
       const int w = nd.width;
       // slopes follow the output layer in the canonical layout
       const float* Sl = P + 3 * w + (int64_t)(nd.depth - 1) * (w * w + w) + nd.d_out * w + nd.d_out;
+      // sin and cos as in training (sin_cos); tanh from the library
       auto phi = [&](float a, int k) {
         const float yv = nd.adaptive ? nd.slope_n * Sl[k - 1] * a : a;
-        return nd.act == ACT_SIN ? sinf(yv) : nd.act == ACT_COS ? cosf(yv) : tanhf(yv);
+        if (nd.act == ACT_TANH) return tanhf(yv);
+        float sn, cs;
+        sin_cos(yv, sn, cs);
+        return nd.act == ACT_SIN ? sn : cs;
       };
       for (int m = 0; m < w; ++m) h[m] = phi(fmaf(P[2 * m], x, fmaf(P[2 * m + 1], y, P[2 * w + m])), 1);
       int64_t off = 3 * w;
