@@ -180,6 +180,26 @@ int ddp_get_params(ddp_problem* p, int sd, float* flat, int on_device);
  * canonical layout (may be NULL).  Stream-ordered. */
 int ddp_loss_and_grad(ddp_problem* p, float* loss_terms, float* grad);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ddp_loss_and_grad with the work counters and the activation stash of its
+ * train kernels in a static device array of the library instead of the
+ * handle's buffers.  The array holds 256 MiB per device (4 KiB of counters,
+ * then stash slots of one workgroup each) from the first call on that device
+ * until the process ends.  The persistent launches run as many workgroups as
+ * stash slots fit, at most as many as the plan's, so a plan that wants more
+ * runs slower; results are those of ddp_loss_and_grad bit for bit (each work
+ * item writes its own gradient and loss rows, summed in a fixed order).
+ * The call launches kernels only: no hipMalloc, hipFree or other allocation
+ * (its first call on a device looks the array's address up once).  All calls
+ * on one device share that device's array, and its counters are zeroed at the
+ * start of each call: calls that overlap on one device race (keep them on one
+ * stream).  Arguments and outputs as for ddp_loss_and_grad.  Errors:
+ * DDP_ESTATE before ddp_finalize or when the problem's device is not the
+ * current one; DDP_EINVAL when one workgroup's stash exceeds the array or the
+ * per-subdomain path needs more than 1024 work counters. */
+int ddp_loss_and_grad_static(ddp_problem* p, float* loss_terms, float* grad);
+
 /* Run n_steps training steps (loss, gradient, Adam with beta = (0.9, 0.999),
  * eps = 1e-8).  loss_terms (device, may be NULL) receives the terms of the
  * last step, evaluated at the parameters before its update. */

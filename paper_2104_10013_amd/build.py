@@ -19,7 +19,7 @@ UNITS = [("kernels.hip", [], "kernels.o")] + \
         [("kernels.hip", ["-DDDP_TRAIN_PDE=%d" % pde], "kernels_pde%d.o" % pde) for pde in range(4)] + \
         [("kernels.hip", ["-DDDP_TRAIN_PDE=%d" % pde, "-DDDP_TRAIN_GA"], "kernels_pde%d_ga.o" % pde)
          for pde in range(4)] + \
-        [("probe.hip", [], "probe.o"), ("ddpinn.cpp", [], "ddpinn.o")]
+        [("probe.hip", [], "probe.o"), ("noalloc.hip", [], "noalloc.o"), ("ddpinn.cpp", [], "ddpinn.o")]
 
 
 def _compile(unit, bdir):

@@ -517,19 +517,39 @@ int reduce_grid(ddp_problem* p, int q0, int q1) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
 }
 
+// Where a step's train launches keep their work counters and activation
+// stash: the plan's own buffers (sized for every resident workgroup, the
+// counters re-armed by the reduction), or a caller-provided region of cap
+// floats (the static scratch) whose counters are zeroed before the launches
+// and whose stash slots bound the persistent grid.
+struct StepBufs {
+  float* scratch;
+  int64_t cap_floats;
+  int* counters;
+};
+
 // kernel sequence of one step (or one loss_and_grad) on stream st
-int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, float* loss_out) {
+int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, float* loss_out,
+                 const StepBufs* b = nullptr) {
   const int n_sd = (int)p->sds.size();
+  float* scratch = b ? b->scratch : p->d_scratch;
+  int* counters = b ? b->counters : p->d_counters;
+  auto slots_for = [&](int n_slots, int64_t slot_floats) {
+    if (!b) return n_slots;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(n_slots, b->cap_floats / std::max<int64_t>(1, slot_floats)));
+  };
+  if (b) HIP_TRY(launch_zero_ints(counters, p->n_counters, st));
   if (p->fused) {
     for (size_t g = 0; g < p->launches.size(); ++g) {
       const ddp_problem::Launch& l = p->launches[g];
       KArgs ka = make_kargs(p);
       ka.items = p->d_titems + l.begin;
       ka.n_items = l.count;
-      ka.counter = p->d_counters + g;
+      ka.counter = counters + g;
+      ka.scratch = scratch;
       ka.scratch_slot = l.slot_floats;
       ka.prologue = g == 0;
-      const int grid = std::max(1, std::min(l.n_slots, l.count));
+      const int grid = std::max(1, std::min(slots_for(l.n_slots, l.slot_floats), l.count));
       HIP_TRY(launch_train(p->pde, l.wpmax, p->ga, ka, grid, st));
     }
     RArgs ra = make_rargs(p);
@@ -537,8 +557,8 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     ra.grad_out = grad_out;
     ra.loss_out = loss_out;
     ra.do_adam = do_adam;
-    ra.counter_reset = p->d_counters;
-    ra.n_counter_reset = (int)p->launches.size();
+    ra.counter_reset = b ? nullptr : p->d_counters;
+    ra.n_counter_reset = b ? 0 : (int)p->launches.size();
     HIP_TRY(launch_reduce(ra, reduce_grid(p, 0, n_sd), st));
     return DDP_OK;
   }
@@ -548,10 +568,11 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     KArgs ka = make_kargs(p);
     ka.items = p->d_titems + p->t_begin[q];
     ka.n_items = p->t_begin[q + 1] - p->t_begin[q];
-    ka.counter = p->d_counters + p->launches.size() + q;
+    ka.counter = counters + p->launches.size() + q;
+    ka.scratch = scratch;
     ka.prologue = q == 0;
     if (ka.n_items == 0 && q != 0) continue;
-    const int grid = std::max(1, std::min(p->n_slots, ka.n_items));
+    const int grid = std::max(1, std::min(slots_for(p->n_slots, p->slot_floats), ka.n_items));
     HIP_TRY(launch_train(p->pde, p->wpmax, p->ga, ka, grid, st));
   }
   for (int q = 0; q < n_sd; ++q) {
@@ -560,8 +581,8 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     ra.grad_out = grad_out;
     ra.loss_out = loss_out;
     ra.do_adam = do_adam;
-    ra.counter_reset = p->d_counters + p->launches.size() + q;
-    ra.n_counter_reset = 1;
+    ra.counter_reset = b ? nullptr : p->d_counters + p->launches.size() + q;
+    ra.n_counter_reset = b ? 0 : 1;
     HIP_TRY(launch_reduce(ra, reduce_grid(p, q, q + 1), st));
   }
   return DDP_OK;
@@ -1089,6 +1110,28 @@ int ddp_get_params(ddp_problem* p, int sd, float* flat, int on_device) {
 int ddp_loss_and_grad(ddp_problem* p, float* loss_terms, float* grad) {
   if (int rc = check_final(p)) return rc;
   return enqueue_step(p, p->stream, 0, grad, loss_terms ? loss_terms : p->d_loss);
+}
+
+int ddp_loss_and_grad_static(ddp_problem* p, float* loss_terms, float* grad) {
+  if (int rc = check_final(p)) return rc;
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != p->device) return fail(DDP_ESTATE, "make the problem's device current before this call");
+  if ((size_t)p->n_counters * sizeof(int) > kStaticCounterBytes)
+    return fail(DDP_EINVAL, "the per-subdomain path of this problem needs " + std::to_string(p->n_counters) +
+                                " work counters; the static scratch holds " +
+                                std::to_string(kStaticCounterBytes / sizeof(int)));
+  int64_t slot = p->fused ? 0 : p->slot_floats;
+  for (const ddp_problem::Launch& l : p->launches) slot = std::max(slot, l.slot_floats);
+  const int64_t cap = (int64_t)((kStaticScratchBytes - kStaticCounterBytes) / sizeof(float));
+  if (slot > cap)
+    return fail(DDP_EINVAL, "one workgroup's activation stash (" + std::to_string(slot * 4) +
+                                " bytes) exceeds the static scratch (" + std::to_string(cap * 4) + " bytes)");
+  void* base = nullptr;
+  HIP_TRY(static_scratch(p->device, &base));
+  const StepBufs b{reinterpret_cast<float*>(static_cast<char*>(base) + kStaticCounterBytes), cap,
+                   static_cast<int*>(base)};
+  return enqueue_step(p, p->stream, 0, grad, loss_terms ? loss_terms : p->d_loss, &b);
 }
 
 int ddp_step(ddp_problem* p, int n_steps, float* loss_terms) {

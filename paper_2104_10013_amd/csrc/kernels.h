@@ -30,6 +30,16 @@ hipError_t launch_pack(const float* params, float* kparams, const NetDesc* nets,
 hipError_t launch_eval(const float* params, const NetDesc* nets, const int* sd_net, int n_sd, int n, const float* xy,
                        const int* owner, float* out, int n_cols, hipStream_t st);
 
+// Static device scratch of the allocation-free entry point (noalloc.hip):
+// kStaticCounterBytes of work counters, then activation stash slots.
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+constexpr size_t kStaticCounterBytes = 4096;
+// device address of the static scratch on device (current); looked up once
+// per device with hipGetSymbolAddress
+hipError_t static_scratch(int device, void** ptr);
+// zero n ints with a kernel (capturable; no memset node)
+hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
+
 // FP32 MFMA rate (TFLOP/s) the device sustains on a pure MFMA loop of iters
 // unrolled steps per wave (probe.hip); synchronous
 hipError_t mfma_probe(int iters, double* tflops);

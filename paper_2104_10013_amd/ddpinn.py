@@ -32,7 +32,7 @@ EXPORTED = [
     "ddp_finalize", "ddp_param_count", "ddp_set_params", "ddp_get_params", "ddp_loss_and_grad",
     "ddp_step", "ddp_get_state", "ddp_set_state", "ddp_eval", "ddp_sync", "ddp_time_kernels",
     "ddp_plan_dump", "ddp_plan", "ddp_last_error", "ddp_destroy", "ddp_autotune", "ddp_mfma_probe",
-    "ddp_time_phases",
+    "ddp_time_phases", "ddp_loss_and_grad_static",
 ]
 
 _METHOD = {W.METHOD_CPINN: DDP_CPINN, W.METHOD_XPINN: DDP_XPINN}
@@ -84,6 +84,7 @@ def load_library(path=LIB_PATH):
         "ddp_autotune": ([P, I, ctypes.c_char_p, pI64], I),
         "ddp_mfma_probe": ([I, ctypes.POINTER(D)], I),
         "ddp_time_phases": ([P, I, pF], I),
+        "ddp_loss_and_grad_static": ([P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -225,6 +226,15 @@ class Problem:
         lt = torch.empty(self.n_sd, 5, dtype=torch.float32, device=self.device)
         g = torch.empty(int(self.offsets[-1]), dtype=torch.float32, device=self.device)
         _check(_lib.ddp_loss_and_grad(self._h, _ptr(lt), _ptr(g)))
+        return lt, g
+
+    def loss_and_grad_static(self):
+        """loss_and_grad through the allocation-free entry point (counters and
+        activation stash in the library's static device scratch); the output
+        tensors are allocated here, by the caller, as for loss_and_grad."""
+        lt = torch.empty(self.n_sd, 5, dtype=torch.float32, device=self.device)
+        g = torch.empty(int(self.offsets[-1]), dtype=torch.float32, device=self.device)
+        _check(_lib.ddp_loss_and_grad_static(self._h, _ptr(lt), _ptr(g)))
         return lt, g
 
     def step(self, n=1):

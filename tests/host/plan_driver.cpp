@@ -85,6 +85,8 @@ static void grid_problem(int method, int pde, int nx, int ny, int seed, bool mix
   // calls that need ddp_finalize
   EXPECT(ddp_step(p, 1, nullptr), DDP_ESTATE);
   EXPECT(ddp_sync(p), DDP_ESTATE);
+  EXPECT(ddp_loss_and_grad_static(p, nullptr, nullptr), DDP_ESTATE);
+  EXPECT(ddp_loss_and_grad_static(nullptr, nullptr, nullptr), DDP_EINVAL);
   EXPECT(ddp_destroy(p), DDP_OK);
 }
 

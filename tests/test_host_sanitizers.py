@@ -23,9 +23,9 @@ def _run(cmd, **kw):
 
 
 def test_host_library_under_sanitizers(tmp_path):
-    objs = [os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "probe.o")] + \
+    objs = [os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "probe.o"), os.path.join(BUILD, "noalloc.o")] + \
         sorted(glob.glob(os.path.join(BUILD, "kernels_pde*.o")))
-    if not shutil.which("g++") or not all(os.path.exists(o) for o in objs[:2]) or len(objs) < 10:
+    if not shutil.which("g++") or not all(os.path.exists(o) for o in objs[:3]) or len(objs) < 11:
         pytest.skip("needs g++ and the kernel objects of paper_2104_10013_amd.build.build()")
     lib_o, drv_o, exe = (str(tmp_path / n) for n in ("ddpinn_san.o", "driver.o", "driver"))
     common = ["g++", "-std=c++17", "-O1", "-g", "-w"] + SAN
