@@ -104,7 +104,9 @@ int ddp_create(ddp_problem** out, int method, int pde, const double* coef, int n
 int ddp_add_subdomain(ddp_problem* p, int n_nets, const int* n_layers, const int* widths,
                       const float* loss_w, float lr, int* sd_id);
 
-/* Set the residual points {x_F} (kind DDP_RESIDUAL; val = forcing f(x), n x
+/* Point sets of a subdomain (Sec. 4.2: residual points, training points of
+ * the data term; Sec. 7.6: the K data of the inverse problem).
+ * Set the residual points {x_F} (kind DDP_RESIDUAL; val = forcing f(x), n x
  * n_eq), training points {x_u} (kind DDP_DATA; val = targets u^(i), n x
  * N_L) or K data points (kind DDP_DATA_AUX, inverse problem; val = K, n x 1)
  * of subdomain sd.  xy is n x 2 interleaved.  Replaces earlier points of
@@ -112,7 +114,9 @@ int ddp_add_subdomain(ddp_problem* p, int n_nets, const int* n_layers, const int
 int ddp_set_points(ddp_problem* p, int sd, int kind, int n, const float* xy, const float* val,
                    int on_device);
 
-/* Add a common interface between sd_a and sd_b (a != b) with n points (n x 2)
+/* Interface points x_I common to two subdomains (Sec. 4.2; the normal n of
+ * the flux term of Eq. cPINNLoss).
+ * Add a common interface between sd_a and sd_b (a != b) with n points (n x 2)
  * and unit normal (pointing from a to b) used by the cPINN flux term.  Both
  * networks are evaluated at the same points.  *if_id receives its index. */
 int ddp_add_interface(ddp_problem* p, int sd_a, int sd_b, int n, const float* xy,
@@ -144,7 +148,10 @@ int ddp_set_interface_method(ddp_problem* p, int if_id, int method);
 /* Set a tuning option (see DDP_OPT_*).  Valid before ddp_finalize. */
 int ddp_set_option(ddp_problem* p, int option, int64_t value);
 
-/* Validate, pack points and parameters into device memory, build the work
+/* The set-up before Algorithm 1's iterations: every subdomain's data on the
+ * one GPU (the paper's one rank per subdomain becomes one persistent launch
+ * over all of them).
+ * Validate, pack points and parameters into device memory, build the work
  * list, and (fused = 1) capture one training step as a HIP graph on
  * hip_stream (a hipStream_t, or NULL for the null stream).  fused = 0 selects
  * the per-subdomain path: the same kernels launched once per subdomain,
@@ -173,7 +180,10 @@ int ddp_param_count(const ddp_problem* p, int sd, int64_t* n);
 int ddp_set_params(ddp_problem* p, int sd, const float* flat, int on_device);
 int ddp_get_params(ddp_problem* p, int sd, float* flat, int on_device);
 
-/* Evaluate the loss of every subdomain and dJ(Theta_q)/dTheta_q (neighbour
+/* The computation stage of Algorithm 1: the loss J(Theta_q) of
+ * Eq. cPINNLoss / Eq. XPINNLoss per subdomain and its gradient, with the
+ * neighbours' interface values as the received (fixed) quantities.
+ * Evaluate the loss of every subdomain and dJ(Theta_q)/dTheta_q (neighbour
  * interface values held fixed), without updating parameters.
  * loss_terms: device, n_sd x 5 = (J, MSE_u, MSE_F, MSE_uavg, MSE_flux|MSE_R).
  * grad: device, all subdomains' gradients concatenated in subdomain order,
@@ -200,7 +210,9 @@ int ddp_loss_and_grad(ddp_problem* p, float* loss_terms, float* grad);
  * per-subdomain path needs more than 1024 work counters. */
 int ddp_loss_and_grad_static(ddp_problem* p, float* loss_terms, float* grad);
 
-/* Run n_steps training steps (loss, gradient, Adam with beta = (0.9, 0.999),
+/* Algorithm 1's iteration with the optimiser of Sec. 6 (Adam), one
+ * optimiser per subdomain with its own learning rate.
+ * Run n_steps training steps (loss, gradient, Adam with beta = (0.9, 0.999),
  * eps = 1e-8).  loss_terms (device, may be NULL) receives the terms of the
  * last step, evaluated at the parameters before its update. */
 int ddp_step(ddp_problem* p, int n_steps, float* loss_terms);
@@ -210,7 +222,9 @@ int ddp_step(ddp_problem* p, int n_steps, float* loss_terms);
 int ddp_get_state(ddp_problem* p, float* m, float* v, int64_t* t);
 int ddp_set_state(ddp_problem* p, const float* m, const float* v, int64_t t);
 
-/* Stitched solution of Eq. FSol at n points (device xy, n x 2).  owner (device,
+/* Stitched solution of Eq. FSol at n points (device xy, n x 2).  The
+ * indicator of Eq. FSol is geometry the library does not hold (it has point
+ * sets, not subdomain shapes), so the caller supplies it: owner (device,
  * n x 4 int32, -1 padded) lists the subdomains whose closure holds each point;
  * the output (device, n x N_L; n x 2 = (u, K) for DDP_DIFFUSION2D_INV)
  * averages their networks (indicator 1/S). */
