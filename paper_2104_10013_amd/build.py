@@ -13,12 +13,13 @@ ARCH = "gfx950"
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # (source, extra flags, object): the train kernels of each of the four
-# operators, plain and with the general activation rule, each in a
-# translation unit of their own, compiled in parallel
+# operators and two activation-stash policies, plain and with the general
+# activation rule, each in a translation unit of their own, compiled in
+# parallel
 UNITS = [("kernels.hip", [], "kernels.o")] + \
-        [("kernels.hip", ["-DDDP_TRAIN_PDE=%d" % pde], "kernels_pde%d.o" % pde) for pde in range(4)] + \
-        [("kernels.hip", ["-DDDP_TRAIN_PDE=%d" % pde, "-DDDP_TRAIN_GA"], "kernels_pde%d_ga.o" % pde)
-         for pde in range(4)] + \
+        [("kernels.hip", ["-DDDP_TRAIN_PDE=%d" % pde, "-DDDP_TRAIN_RH=%d" % rh] + (["-DDDP_TRAIN_GA"] if ga else []),
+          "kernels_pde%d_rh%d%s.o" % (pde, rh, "_ga" if ga else ""))
+         for pde in range(4) for rh in range(2) for ga in (False, True)] + \
         [("probe.hip", [], "probe.o"), ("noalloc.hip", [], "noalloc.o"), ("ddpinn.cpp", [], "ddpinn.o")]
 
 
@@ -35,7 +36,7 @@ def _compile(unit, bdir):
 def build(verbose=True):
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(UNITS), os.cpu_count() or 8)) as ex:
         objs = list(ex.map(lambda u: _compile(u, bdir), UNITS))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs

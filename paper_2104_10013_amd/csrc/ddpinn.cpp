@@ -82,6 +82,7 @@ struct ddp_problem {
   int64_t chunk_points = 1024;  // upper bound of points per work item
   int blocks_per_cu = 0;         // 0: from the occupancy query
   int items_per_slot = 4;        // work items per resident workgroup the plan aims for
+  int recompute = 0;             // activation policy: 1 stash a^k and rebuild h^k in the reverse pass, 0 stash both
 
   // plan
   bool planned = false, finalized = false;
@@ -550,7 +551,7 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
       ka.scratch_slot = l.slot_floats;
       ka.prologue = g == 0;
       const int grid = std::max(1, std::min(slots_for(l.n_slots, l.slot_floats), l.count));
-      HIP_TRY(launch_train(p->pde, l.wpmax, p->ga, ka, grid, st));
+      HIP_TRY(launch_train(p->pde, l.wpmax, p->ga, p->recompute, ka, grid, st));
     }
     RArgs ra = make_rargs(p);
     reduce_range(p, ra, 0, n_sd);
@@ -573,7 +574,7 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
     ka.prologue = q == 0;
     if (ka.n_items == 0 && q != 0) continue;
     const int grid = std::max(1, std::min(slots_for(p->n_slots, p->slot_floats), ka.n_items));
-    HIP_TRY(launch_train(p->pde, p->wpmax, p->ga, ka, grid, st));
+    HIP_TRY(launch_train(p->pde, p->wpmax, p->ga, p->recompute, ka, grid, st));
   }
   for (int q = 0; q < n_sd; ++q) {
     RArgs ra = make_rargs(p);
@@ -788,6 +789,10 @@ int ddp_set_option(ddp_problem* p, int option, int64_t value) {
       if (value < 1 || value > 64) return fail(DDP_EINVAL, "items per slot out of range");
       p->items_per_slot = (int)value;
       break;
+    case DDP_OPT_RECOMPUTE:
+      if (value != 0 && value != 1) return fail(DDP_EINVAL, "recompute must be 0 or 1");
+      p->recompute = (int)value;
+      break;
     default:
       return fail(DDP_EINVAL, "unknown option");
   }
@@ -817,18 +822,20 @@ int install_plan(ddp_problem* p) {
   if (p->stream) HIP_TRY(hipStreamSynchronize(p->stream));
   for (void* a : p->plan_allocations) hipFree(a);
   p->plan_allocations.clear();
+  HIP_TRY(train_occupancy(p->pde, p->wpmax, p->ga, p->recompute, &p->occupancy));
+  if (p->occupancy < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
   const int bpc = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, p->occupancy) : p->occupancy;
   p->n_slots = std::max(1, p->n_cu * bpc);
   p->plan_slots = p->n_slots;
   if (int rc = build_plan(p)) return rc;
-  p->slot_floats = scratch_slot_floats(p->pde, p->wpmax);
+  p->slot_floats = scratch_slot_floats(p->pde, p->wpmax, p->recompute);
   int64_t scratch_floats = (int64_t)p->n_slots * p->slot_floats;
   for (ddp_problem::Launch& l : p->launches) {
-    HIP_TRY(train_occupancy(p->pde, l.wpmax, p->ga, &l.occupancy));
+    HIP_TRY(train_occupancy(p->pde, l.wpmax, p->ga, p->recompute, &l.occupancy));
     if (l.occupancy < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
     const int b = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, l.occupancy) : l.occupancy;
     l.n_slots = std::max(1, p->n_cu * b);
-    l.slot_floats = scratch_slot_floats(p->pde, l.wpmax);
+    l.slot_floats = scratch_slot_floats(p->pde, l.wpmax, p->recompute);
     scratch_floats = std::max(scratch_floats, (int64_t)l.n_slots * l.slot_floats);
   }
   // counters: one per fused launch, then one per subdomain (plain path)
@@ -906,14 +913,15 @@ bool cache_lookup(const char* path, uint64_t sig, int64_t* cfg) {
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
     unsigned long long s = 0;
-    long long c = 0, ips = 0, bpc = 0;
+    long long c = 0, ips = 0, bpc = 0, rh = 0;
     if (std::sscanf(line, "{\"signature\": \"%llx\", \"chunk_points\": %lld, \"items_per_slot\": %lld, "
-                          "\"blocks_per_cu\": %lld",
-                    &s, &c, &ips, &bpc) == 4 &&
+                          "\"blocks_per_cu\": %lld, \"recompute\": %lld",
+                    &s, &c, &ips, &bpc, &rh) == 5 &&
         s == sig) {
       cfg[0] = c;
       cfg[1] = ips;
       cfg[2] = bpc;
+      cfg[3] = rh;
       found = true;  // the last entry for a signature wins
     }
   }
@@ -933,7 +941,7 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   HIP_TRY(hipGetDevice(&p->device));
   p->stream = static_cast<hipStream_t>(hip_stream);
   HIP_TRY(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
-  HIP_TRY(train_occupancy(p->pde, p->wpmax, p->ga, &p->occupancy));
+  HIP_TRY(train_occupancy(p->pde, p->wpmax, p->ga, p->recompute, &p->occupancy));
   if (p->occupancy < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
 
   int rc = 0;
@@ -967,13 +975,11 @@ namespace {
 // three fastest again over three interleaved rounds; best receives the
 // winner.  Leaves the last candidate installed.
 int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, float* best_ms) {
-  int max_occ = p->occupancy;   // the fused launches may run narrower kernels
-  for (const ddp_problem::Launch& l : p->launches) max_occ = std::max(max_occ, l.occupancy);
   const int64_t chunks[] = {256, 512, 1024, 2048};
   const int ipss[] = {1, 2, 4, 8};
   struct Cand {
     int64_t c;
-    int ips, bpc;
+    int ips, bpc, rh;
     float ms;
   };
   std::vector<Cand> cands;
@@ -983,6 +989,7 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
     p->chunk_points = k.c;
     p->items_per_slot = k.ips;
     p->blocks_per_cu = k.bpc;
+    p->recompute = k.rh;
     if (int rc = install_plan(p)) return rc;
     if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
     HIP_TRY(hipEventRecord(ev[0], p->stream));
@@ -994,13 +1001,21 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
     *ms /= n;
     return DDP_OK;
   };
-  for (int64_t c : chunks)
-    for (int ips : ipss)
-      for (int bpc = 1; bpc <= max_occ; ++bpc) {
-        Cand k{c, ips, bpc, 0.f};
-        if (int rc = time_cand(k, iters, &k.ms)) return rc;
-        cands.push_back(k);
-      }
+  for (int rh = 0; rh <= 1; ++rh) {
+    // resident workgroups per CU of this policy's kernels (the fused
+    // launches may run narrower kernels than the per-subdomain path)
+    p->recompute = rh;
+    if (int rc = install_plan(p)) return rc;
+    int max_occ = p->occupancy;
+    for (const ddp_problem::Launch& l : p->launches) max_occ = std::max(max_occ, l.occupancy);
+    for (int64_t c : chunks)
+      for (int ips : ipss)
+        for (int bpc = 1; bpc <= max_occ; ++bpc) {
+          Cand k{c, ips, bpc, rh, 0.f};
+          if (int rc = time_cand(k, iters, &k.ms)) return rc;
+          cands.push_back(k);
+        }
+  }
   // the leading candidates are often within a percent of each other: time the
   // best three again, interleaved over three rounds of 2 x iters passes, and
   // keep the smallest total
@@ -1020,6 +1035,7 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
       best[0] = cands[k].c;
       best[1] = cands[k].ips;
       best[2] = cands[k].bpc;
+      best[3] = cands[k].rh;
     }
   return DDP_OK;
 }
@@ -1030,15 +1046,19 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
   if (int rc = check_final(p)) return rc;
   if (iters < 1) return fail(DDP_EINVAL, "iters must be >= 1");
   const uint64_t sig = problem_signature(p);
-  const int64_t prev[3] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu};
-  int64_t best[3] = {prev[0], prev[1], prev[2]};
+  const int64_t prev[4] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu, p->recompute};
+  int64_t best[4] = {prev[0], prev[1], prev[2], prev[3]};
+  auto apply = [&](const int64_t* v) {
+    p->chunk_points = v[0];
+    p->items_per_slot = (int)v[1];
+    p->blocks_per_cu = (int)v[2];
+    p->recompute = (int)v[3];
+  };
   // on any failure the previous plan is put back, so the handle stays usable;
   // if even that fails, every later call reports DDP_ESTATE
   auto restore = [&](int rc) {
     const std::string msg = g_err;
-    p->chunk_points = prev[0];
-    p->items_per_slot = (int)prev[1];
-    p->blocks_per_cu = (int)prev[2];
+    apply(prev);
     install_plan(p);
     g_err = msg;
     return rc;
@@ -1059,21 +1079,17 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
       if (f) {
         std::fprintf(f,
                      "{\"signature\": \"%016llx\", \"chunk_points\": %lld, \"items_per_slot\": %lld, "
-                     "\"blocks_per_cu\": %lld, \"ms\": %.5f}\n",
-                     (unsigned long long)sig, (long long)best[0], (long long)best[1], (long long)best[2], best_ms);
+                     "\"blocks_per_cu\": %lld, \"recompute\": %lld, \"ms\": %.5f}\n",
+                     (unsigned long long)sig, (long long)best[0], (long long)best[1], (long long)best[2],
+                     (long long)best[3], best_ms);
         std::fclose(f);
       }
     }
   }
-  p->chunk_points = best[0];
-  p->items_per_slot = (int)best[1];
-  p->blocks_per_cu = (int)best[2];
+  apply(best);
   if (int rc = install_plan(p)) return restore(rc);
-  if (choice) {
-    choice[0] = best[0];
-    choice[1] = best[1];
-    choice[2] = best[2];
-  }
+  if (choice)
+    for (int k = 0; k < 4; ++k) choice[k] = best[k];
   return DDP_OK;
 }
 
@@ -1238,7 +1254,7 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
           }
           if (ka.n_items == 0) continue;
           const int grid = std::max(1, std::min(n_slots, ka.n_items));
-          HIP_TRY(launch_train(p->pde, wpmax, p->ga, ka, grid, p->stream));
+          HIP_TRY(launch_train(p->pde, wpmax, p->ga, p->recompute, ka, grid, p->stream));
         }
       } else {
         RArgs ra = make_rargs(p);
@@ -1301,7 +1317,8 @@ int ddp_time_phases(ddp_problem* p, int iters, float* ms) {
           ka.n_items = count[g];
           ka.counter = p->d_counters + g;
           ka.scratch_slot = l.slot_floats;
-          hip_ok(launch_train(p->pde, l.wpmax, p->ga, ka, std::max(1, std::min(l.n_slots, count[g])), p->stream));
+          hip_ok(launch_train(p->pde, l.wpmax, p->ga, p->recompute, ka, std::max(1, std::min(l.n_slots, count[g])),
+                              p->stream));
         }
         float t = 0.f;
         if (hip_ok(hipEventRecord(ev[1], p->stream)) && hip_ok(hipEventSynchronize(ev[1])) &&
@@ -1324,8 +1341,8 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   if (!p->planned) return fail(DDP_ESTATE, "no plan: call ddp_plan or ddp_finalize first");
   FILE* f = std::fopen(json_path, "w");
   if (!f) return fail(DDP_EINVAL, std::string("cannot open ") + json_path);
-  std::fprintf(f, "{\"method\": %d, \"pde\": %d, \"fused\": %d, \"wpmax\": %d, \"tile_points\": %d,\n", p->method,
-               p->pde, p->fused, p->wpmax, kTilePts);
+  std::fprintf(f, "{\"method\": %d, \"pde\": %d, \"fused\": %d, \"wpmax\": %d, \"tile_points\": %d, \"recompute\": %d,\n",
+               p->method, p->pde, p->fused, p->wpmax, kTilePts, p->recompute);
   std::fprintf(f, "\"nets\": [");
   for (size_t q = 0; q < p->nets.size(); ++q) {
     const NetDesc& n = p->nets[q];

@@ -7,18 +7,19 @@ namespace ddp {
 
 // dynamic LDS bytes of the train kernel for a width class
 size_t lds_bytes(int pde, int wpmax);
-// floats of one workgroup's activation stash for the widest class wpmax
-int64_t scratch_slot_floats(int pde, int wpmax);
+// floats of one workgroup's activation stash for the widest class wpmax;
+// rh: the recompute policy (a^k stashed, h^{k-1} rebuilt in the reverse pass)
+int64_t scratch_slot_floats(int pde, int wpmax, bool rh);
 // width group of the kernel that runs classes up to wpmax: the class itself,
 // or with the general activation rule (ga) the group up to 80 or up to 112
 int kernel_wpmax(int wpmax, bool ga);
 // resident train workgroups per compute unit (also raises the LDS limit)
-hipError_t train_occupancy(int pde, int wpmax, bool ga, int* blocks_per_cu);
+hipError_t train_occupancy(int pde, int wpmax, bool ga, bool rh, int* blocks_per_cu);
 
 // persistent loss + gradient-partial kernel over ka.items (ka.prologue:
 // settle the Adam step counter first); ga: the general-activation kernel
-// (wpmax from kernel_wpmax)
-hipError_t launch_train(int pde, int wpmax, bool ga, const KArgs& ka, int grid, hipStream_t st);
+// (wpmax from kernel_wpmax); rh: the recompute policy's kernel
+hipError_t launch_train(int pde, int wpmax, bool ga, bool rh, const KArgs& ka, int grid, hipStream_t st);
 // set a work counter to zero
 hipError_t launch_reset_counter(int* c, hipStream_t st);
 // gradient reduction, loss reduction and optional Adam; re-arms ra.counter_reset

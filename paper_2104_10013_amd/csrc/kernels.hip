@@ -343,6 +343,19 @@ __device__ __forceinline__ float act_stream(int s, float a, float ax, float ay, 
   return fmaf(s1, al, -2.f * t * s1 * q);
 }
 
+// one stream of the general activation rule (slope c, activation act)
+template <bool S2>
+__device__ __forceinline__ float act_stream_ga(int s, int act, float c, float a, float ax, float ay, float al) {
+  const float y = c * a, yx = c * ax, yy = c * ay, yl = c * al;
+  float f0, f1, f2, f3;
+  act_derivs(act, y, f0, f1, f2, f3);
+  if (s == 0) return f0;
+  if (s == 1) return f1 * yx;
+  if (s == 2) return f1 * yy;
+  const float q = S2 ? fmaf(yx, yx, yy * yy) : yx * yx;
+  return fmaf(f1, yl, f2 * q);
+}
+
 template <int WP, int PDE>
 struct Tile {
   static constexpr int MB = WP / 16;
@@ -752,7 +765,7 @@ struct Tile {
     if (lane == 0) sSl[wave] = dc;
   }
 
-  template <bool PREFETCH_A, int MODE, int PHASE, bool GA>
+  template <bool PREFETCH_A, int MODE, int PHASE, bool GA, bool RH>
   __device__ __forceinline__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                    float* slot, int64_t slot_floats, const float* sNb, float* sInv, int t_lo,
                                    int t_hi, int roff) {
@@ -808,7 +821,7 @@ struct Tile {
         g = lane >> 4;
         pc = lane & 15;
         tp = wave * 16 + pc;
-        stash_store(rs, 1, k - 2, wave, lane, H);   // h^{k-1}
+        if constexpr (!RH) stash_store(rs, 1, k - 2, wave, lane, H);   // h^{k-1}
         __syncthreads();
         stage_wb(sW, K + L.k_w(k), K + L.k_b(k), tid);
         __syncthreads();
@@ -882,7 +895,7 @@ struct Tile {
       // a^D for the first reverse layer, loaded while the output layer runs
       // (where registers allow; else at the top of each reverse layer)
       Streams Ak;
-      if (PREFETCH_A && D >= 2) stash_load(rs, 0, D - 2, wave, lane, Ak);
+      if ((PREFETCH_A || RH) && D >= 2) stash_load(rs, 0, D - 2, wave, lane, Ak);
       float accL[KL];
 #pragma unroll
       for (int r = 0; r < KL; ++r) {
@@ -953,7 +966,7 @@ struct Tile {
         // abar^k from the stashed a^k (loaded ahead) and the incoming g^k (in place
         // of g^k); with a general activation also the layer's slope gradient
         {
-          if (!PREFETCH_A) stash_load(rs, 0, k - 2, wave, lane, Ak);
+          if (!PREFETCH_A && !RH) stash_load(rs, 0, k - 2, wave, lane, Ak);
           const float ck = GA ? slope(nd, K, L, k) : 1.f;
           float dc = 0.f;
 #pragma unroll
@@ -975,6 +988,12 @@ struct Tile {
           }
           if constexpr (GA) slope_wave_sum(dc, sSl, lane, wave);
         }
+        // recompute policy: a^{k-1} now (the stash for k - 1 >= 2, layer 1
+        // from the point itself), h^{k-1} rebuilt from it stream by stream below
+        if constexpr (RH) {
+          if (k > 2) stash_load(rs, 0, k - 3, wave, lane, Ak);
+          else layer1(K, x, y, g, Ak);
+        }
         Streams& Ab = G;
         __syncthreads();
         stage(sW, K + L.k_wt(k), tid);
@@ -990,7 +1009,20 @@ struct Tile {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           f4 Hs[MB];
-          stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s (stored in the forward)
+          if constexpr (RH) {   // h^{k-1}_s = the activation rule on a^{k-1}
+            const float cp = GA ? slope(nd, K, L, k - 1) : 1.f;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if constexpr (GA)
+                  Hs[mb][i] = act_stream_ga<S2>(s, nd.act, cp, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
+                else
+                  Hs[mb][i] = act_stream<S2>(s, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
+              }
+          } else {
+            stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s (stored in the forward)
+          }
           {
             f4 Gs[MB];
             hidden_bwd_stream(sW, g, pc, real_steps(nd.width), Ab[s], Gs);
@@ -1006,7 +1038,7 @@ struct Tile {
             for (int mb = 0; mb < MB; ++mb) G[s][mb] = Gs[mb];   // g^{k-1}_s replaces abar^k_s
           }
           // a^{k-1} for the next reverse layer, loaded during the last dW^k stream
-          if (PREFETCH_A && s == 3 && k > 2) stash_load(rs, 0, k - 3, wave, lane, Ak);
+          if (PREFETCH_A && !RH && s == 3 && k > 2) stash_load(rs, 0, k - 3, wave, lane, Ak);
           __syncthreads();
 #pragma unroll
           for (int r = 0; r < NB; ++r) {
@@ -1102,11 +1134,11 @@ struct Tile {
   // registers, so it is used for classes up to 48 in kernels that run two
   // waves per SIMD anyway because of a wider class
   // (GA as in values_tile)
-  template <int WPMAX, int MODE, int PHASE, bool GA>
+  template <int WPMAX, int MODE, int PHASE, bool GA, bool RH>
   __device__ __forceinline__ static void train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds, float* slot,
                                int64_t slot_floats, const float* sNb, float* sInv, int t_lo, int t_hi, int roff) {
-    run_train<(WP <= 48 && WPMAX >= 48), MODE, PHASE, GA>(ka, it, nd, lds, slot, slot_floats, sNb, sInv, t_lo, t_hi,
-                                                           roff);
+    run_train<(WP <= 48 && WPMAX >= 48), MODE, PHASE, GA, RH>(ka, it, nd, lds, slot, slot_floats, sNb, sInv, t_lo,
+                                                               t_hi, roff);
   }
 };
 
@@ -1135,7 +1167,7 @@ constexpr int lds_train_bytes() {
 // A paired item of the inverse problem goes tile by tile: the neighbour's K-
 // and u-networks (interfaces), the own K-network's streams, the u-network's
 // train pass (loss, u seeds, K seeds), then the K-network's train pass.
-template <int WPMAX, int PDE, bool GA>
+template <int WPMAX, int PDE, bool GA, bool RH>
 __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                          float* slot) {
   float* sNb = lds + lds_tile_floats<WPMAX, PDE>();
@@ -1177,11 +1209,11 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
           DDP_SWITCH(nbu.wclass, template values_tile<VAL_INV_NB, GA>(ka, it, nbu, lds, sNb, sInv + 6 * TP, t0))
           __syncthreads();
         }
-        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_FWD, GA>(ka, it, ndk, lds, slot + half, half,
+        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_FWD, GA, RH>(ka, it, ndk, lds, slot + half, half,
                                                                             sNb, sInv, t0, t0 + 1, nd.gsize))
         DDP_SWITCH(nd.wclass,
-                   template train<WPMAX, EPI_INV_U, PH_ALL, GA>(ka, it, nd, lds, slot, half, sNb, sInv, t0, t0 + 1, 0))
-        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_BWD, GA>(ka, it, ndk, lds, slot + half, half,
+                   template train<WPMAX, EPI_INV_U, PH_ALL, GA, RH>(ka, it, nd, lds, slot, half, sNb, sInv, t0, t0 + 1, 0))
+        DDP_SWITCH(ndk.wclass, template train<WPMAX, EPI_SEED, PH_BWD, GA, RH>(ka, it, ndk, lds, slot + half, half,
                                                                             sNb, sInv, t0, t0 + 1, nd.gsize))
       }
       return;
@@ -1193,7 +1225,7 @@ __device__ __forceinline__ void dispatch(const KArgs& ka, const Item& it, const 
     DDP_SWITCH(ndn.wclass, template values_tile<VAL_OWN, GA>(ka, it, ndn, lds, sNb, nullptr, 0))
     __syncthreads();
   }
-  DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_OWN, PH_ALL, GA>(ka, it, nd, lds, slot,
+  DDP_SWITCH(nd.wclass, template train<WPMAX, EPI_OWN, PH_ALL, GA, RH>(ka, it, nd, lds, slot,
                                                        PDE == PDE_INV ? ka.scratch_slot / 2 : ka.scratch_slot, sNb,
                                                        sInv, 0, it.count, 0))
 #undef DDP_SWITCH
@@ -1212,7 +1244,7 @@ constexpr int min_waves_per_eu() {
 // GA: kernels with the general activation rule, launched for problems where a
 // network uses another activation than tanh or trainable slopes (built for
 // the class groups up to 80 and up to 112 only)
-template <int WPMAX, int PDE, bool GA>
+template <int WPMAX, int PDE, bool GA, bool RH>
 __global__ __launch_bounds__(NT, min_waves_per_eu<WPMAX>()) void k_train(KArgs ka) {
   // one 16-byte aligned dynamic LDS block: the tile buffers, then the slot
   // that broadcasts the next work item (no static LDS, so the float4
@@ -1233,7 +1265,7 @@ __global__ __launch_bounds__(NT, min_waves_per_eu<WPMAX>()) void k_train(KArgs k
     if (idx >= ka.n_items) break;
     const Item it = ka.items[idx];
     const NetDesc nd = ka.nets[it.q];
-    dispatch<WPMAX, PDE, GA>(ka, it, nd, lds, slot);
+    dispatch<WPMAX, PDE, GA, RH>(ka, it, nd, lds, slot);
   }
 }
 
@@ -1485,70 +1517,80 @@ static int wclass_index(int wpmax) {
   return -1;
 }
 
-template <int PDE>
+// Train kernels per operator and activation policy RH (0: the forward
+// stashes a^k and h^k; 1: it stashes a^k only and the reverse pass rebuilds
+// h^{k-1} from a^{k-1}), and the LDS bytes per class (policy-independent).
+template <int PDE, int RH>
 struct KTable {
   static const void* train[7];
   static const void* train_ga[2];   // general activation: class groups up to 80, up to 112
+};
+template <int PDE>
+struct KLds {
   static int lds[7];
 };
 // (a unit built with DDP_TRAIN_GA defines the general-activation row of its
-// operator, one without it the plain row and the LDS sizes)
+// operator and policy, one without it the plain row, and with policy 0 also
+// the LDS sizes)
+#ifndef DDP_TRAIN_RH
+#define DDP_TRAIN_RH 0
+#endif
 #ifdef DDP_TRAIN_GA
-#define DDP_ROW(PDE)                                                                                              \
-  template <> const void* KTable<PDE>::train_ga[2] = {(const void*)k_train<80, PDE, true>,                        \
-                                                      (const void*)k_train<112, PDE, true>};
+#define DDP_ROW(PDE, RH)                                                                                          \
+  template <> const void* KTable<PDE, RH>::train_ga[2] = {(const void*)k_train<80, PDE, true, RH>,                \
+                                                          (const void*)k_train<112, PDE, true, RH>};
 #else
-#define DDP_ROW(PDE)                                                                                              \
-  template <> const void* KTable<PDE>::train[7] = {                                                               \
-      (const void*)k_train<16, PDE, false>, (const void*)k_train<32, PDE, false>,                                 \
-      (const void*)k_train<48, PDE, false>, (const void*)k_train<64, PDE, false>,                                 \
-      (const void*)k_train<80, PDE, false>, (const void*)k_train<96, PDE, false>,                                 \
-      (const void*)k_train<112, PDE, false>};                                                                     \
-  template <> int KTable<PDE>::lds[7] = {                                                       \
-      lds_train_bytes<16, PDE>(), lds_train_bytes<32, PDE>(), lds_train_bytes<48, PDE>(),       \
-      lds_train_bytes<64, PDE>(), lds_train_bytes<80, PDE>(), lds_train_bytes<96, PDE>(),       \
-      lds_train_bytes<112, PDE>()};
+#define DDP_ROW(PDE, RH)                                                                                          \
+  template <> const void* KTable<PDE, RH>::train[7] = {                                                           \
+      (const void*)k_train<16, PDE, false, RH>, (const void*)k_train<32, PDE, false, RH>,                         \
+      (const void*)k_train<48, PDE, false, RH>, (const void*)k_train<64, PDE, false, RH>,                         \
+      (const void*)k_train<80, PDE, false, RH>, (const void*)k_train<96, PDE, false, RH>,                         \
+      (const void*)k_train<112, PDE, false, RH>};
 #endif
 #ifdef DDP_TRAIN_PDE
-DDP_ROW(DDP_TRAIN_PDE)
+DDP_ROW(DDP_TRAIN_PDE, (DDP_TRAIN_RH != 0))
+#if !defined(DDP_TRAIN_GA) && DDP_TRAIN_RH == 0
+template <> int KLds<DDP_TRAIN_PDE>::lds[7] = {
+    lds_train_bytes<16, DDP_TRAIN_PDE>(), lds_train_bytes<32, DDP_TRAIN_PDE>(), lds_train_bytes<48, DDP_TRAIN_PDE>(),
+    lds_train_bytes<64, DDP_TRAIN_PDE>(), lds_train_bytes<80, DDP_TRAIN_PDE>(), lds_train_bytes<96, DDP_TRAIN_PDE>(),
+    lds_train_bytes<112, DDP_TRAIN_PDE>()};
+#endif
 #undef DDP_ROW
 #else
 #undef DDP_ROW
 // the tables are defined in the operators' own translation units
-template <> const void* KTable<PDE_POISSON>::train[7];
-template <> const void* KTable<PDE_BURGERS>::train[7];
-template <> const void* KTable<PDE_NS>::train[7];
-template <> const void* KTable<PDE_INV>::train[7];
-template <> const void* KTable<PDE_POISSON>::train_ga[2];
-template <> const void* KTable<PDE_BURGERS>::train_ga[2];
-template <> const void* KTable<PDE_NS>::train_ga[2];
-template <> const void* KTable<PDE_INV>::train_ga[2];
-template <> int KTable<PDE_POISSON>::lds[7];
-template <> int KTable<PDE_BURGERS>::lds[7];
-template <> int KTable<PDE_NS>::lds[7];
-template <> int KTable<PDE_INV>::lds[7];
+#define DDP_DECL(PDE)                                                  \
+  template <> const void* KTable<PDE, false>::train[7];                \
+  template <> const void* KTable<PDE, true>::train[7];                 \
+  template <> const void* KTable<PDE, false>::train_ga[2];             \
+  template <> const void* KTable<PDE, true>::train_ga[2];              \
+  template <> int KLds<PDE>::lds[7];
+DDP_DECL(PDE_POISSON)
+DDP_DECL(PDE_BURGERS)
+DDP_DECL(PDE_NS)
+DDP_DECL(PDE_INV)
+#undef DDP_DECL
 
-static const void* pick(int pde, int wpmax, bool ga) {
-  const int c = wclass_index(wpmax);
-  if (c < 0) return nullptr;
-  if (ga) {   // general-activation kernels exist for the groups up to 80 and up to 112
-    if (wpmax != 80 && wpmax != 112) return nullptr;
-    const int g = wpmax == 80 ? 0 : 1;
-    switch (pde) {
-      case PDE_POISSON: return KTable<PDE_POISSON>::train_ga[g];
-      case PDE_BURGERS: return KTable<PDE_BURGERS>::train_ga[g];
-      case PDE_NS: return KTable<PDE_NS>::train_ga[g];
-      case PDE_INV: return KTable<PDE_INV>::train_ga[g];
-    }
-    return nullptr;
-  }
+template <int RH>
+static const void* pick_rh(int pde, int c, bool ga, int g) {
   switch (pde) {
-    case PDE_POISSON: return KTable<PDE_POISSON>::train[c];
-    case PDE_BURGERS: return KTable<PDE_BURGERS>::train[c];
-    case PDE_NS: return KTable<PDE_NS>::train[c];
-    case PDE_INV: return KTable<PDE_INV>::train[c];
+    case PDE_POISSON: return ga ? KTable<PDE_POISSON, RH>::train_ga[g] : KTable<PDE_POISSON, RH>::train[c];
+    case PDE_BURGERS: return ga ? KTable<PDE_BURGERS, RH>::train_ga[g] : KTable<PDE_BURGERS, RH>::train[c];
+    case PDE_NS: return ga ? KTable<PDE_NS, RH>::train_ga[g] : KTable<PDE_NS, RH>::train[c];
+    case PDE_INV: return ga ? KTable<PDE_INV, RH>::train_ga[g] : KTable<PDE_INV, RH>::train[c];
   }
   return nullptr;
+}
+
+static const void* pick(int pde, int wpmax, bool ga, bool rh) {
+  const int c = wclass_index(wpmax);
+  if (c < 0) return nullptr;
+  int g = 0;
+  if (ga) {   // general-activation kernels exist for the groups up to 80 and up to 112
+    if (wpmax != 80 && wpmax != 112) return nullptr;
+    g = wpmax == 80 ? 0 : 1;
+  }
+  return rh ? pick_rh<true>(pde, c, ga, g) : pick_rh<false>(pde, c, ga, g);
 }
 
 size_t lds_bytes(int pde, int wpmax) {
@@ -1556,33 +1598,34 @@ size_t lds_bytes(int pde, int wpmax) {
   if (c < 0) return 0;
   int f = 0;
   switch (pde) {
-    case PDE_POISSON: f = KTable<PDE_POISSON>::lds[c]; break;
-    case PDE_BURGERS: f = KTable<PDE_BURGERS>::lds[c]; break;
-    case PDE_NS: f = KTable<PDE_NS>::lds[c]; break;
-    case PDE_INV: f = KTable<PDE_INV>::lds[c]; break;
+    case PDE_POISSON: f = KLds<PDE_POISSON>::lds[c]; break;
+    case PDE_BURGERS: f = KLds<PDE_BURGERS>::lds[c]; break;
+    case PDE_NS: f = KLds<PDE_NS>::lds[c]; break;
+    case PDE_INV: f = KLds<PDE_INV>::lds[c]; break;
   }
   return (size_t)f;
 }
 
-int64_t scratch_slot_floats(int pde, int wpmax) {
-  // two regions (a^k and h^k) of kMaxDepth - 1 layers; the inverse problem
-  // keeps one such stash per network of a pair
-  const int64_t one = (int64_t)2 * (kMaxDepth - 1) * kWaves * 4 * (wpmax / 16) * 64 * 4;
+int64_t scratch_slot_floats(int pde, int wpmax, bool rh) {
+  // two regions (a^k and h^k) of kMaxDepth - 1 layers, or the a^k region
+  // alone under the recompute policy; the inverse problem keeps one such
+  // stash per network of a pair
+  const int64_t one = (int64_t)(rh ? 1 : 2) * (kMaxDepth - 1) * kWaves * 4 * (wpmax / 16) * 64 * 4;
   return pde == PDE_INV ? 2 * one : one;
 }
 
 int kernel_wpmax(int wpmax, bool ga) { return ga ? (wpmax <= 80 ? 80 : 112) : wpmax; }
 
-hipError_t launch_train(int pde, int wpmax, bool ga, const KArgs& ka, int grid, hipStream_t st) {
-  const void* fn = pick(pde, wpmax, ga);
+hipError_t launch_train(int pde, int wpmax, bool ga, bool rh, const KArgs& ka, int grid, hipStream_t st) {
+  const void* fn = pick(pde, wpmax, ga, rh);
   if (!fn) return hipErrorInvalidValue;
   KArgs a = ka;
   void* args[] = {&a};
   return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds_bytes(pde, wpmax), st);
 }
 
-hipError_t train_occupancy(int pde, int wpmax, bool ga, int* blocks_per_cu) {
-  const void* fn = pick(pde, wpmax, ga);
+hipError_t train_occupancy(int pde, int wpmax, bool ga, bool rh, int* blocks_per_cu) {
+  const void* fn = pick(pde, wpmax, ga, rh);
   if (!fn) return hipErrorInvalidValue;
   const size_t lds = lds_bytes(pde, wpmax);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

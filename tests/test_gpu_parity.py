@@ -284,6 +284,7 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     pb, lt0, g0 = run(prob)
     cache = tmp_path / "tune.jsonl"
     choice = pb.autotune(iters=2, cache_path=cache)
+    assert choice["recompute"] in (0, 1)
     assert cache.exists() and len(cache.read_text().splitlines()) == 1
     lt1, g1 = pb.loss_and_grad()
     torch.cuda.synchronize()
@@ -683,3 +684,20 @@ def test_many_subdomains_random_widths_and_depths():
         wl, wg = compare(prob, params, lt, g)
         _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
         pb.close()
+
+
+@pytest.mark.parametrize("name,scale", [("c2_xpinn_poisson", 0.1), ("c5_xpinn_inverse_diffusion", 0.03),
+                                        ("c5_table4_adaptive", 0.1), ("c3_cpinn_burgers", 0.2)])
+def test_recompute_policy(name, scale):
+    """Both activation policies (stash a^k and h^k; stash a^k and rebuild h^k
+    in the reverse pass) against the oracle, on both paths."""
+    prob = W.make_problem(name, seed=0, scale=scale)
+    params = _params(prob, 5)
+    ref = oracle.loss_and_grad(prob, params)
+    for fused in (True, False):
+        for rh in (0, 1):
+            _say(f"{name} scale {scale} fused {fused} recompute {rh}")
+            pb, lt, g = run(prob, params, fused=fused, recompute=rh)
+            wl, wg = compare(prob, params, lt, g, ref=ref)
+            _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+            pb.close()
