@@ -65,6 +65,20 @@ __device__ __forceinline__ int item_tid() {
   return t;
 }
 
+// Asynchronous copy of n4 float4 (16-byte aligned at both ends) from global
+// memory straight into LDS (gfx950 LDS DMA, no registers): wave `wave`
+// copies the 1 KB blocks wave, wave + kWaves, ...; lane l of a block moves
+// its 16 bytes to block base + 16 l.  The data is complete at the next
+// workgroup barrier (the compiler waits on the load counter there).
+__device__ __forceinline__ void dma_to_lds(float* dst, const float* src, int n4, int wave, int lane) {
+  for (int b = wave; b * 64 < n4; b += kWaves) {
+    const int c = b * 64 + lane;
+    if (c < n4)
+      __builtin_amdgcn_global_load_lds(src + 4 * c, (__attribute__((address_space(3))) void*)(dst + 256 * b), 16, 0,
+                                       0);
+  }
+}
+
 __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -412,6 +426,22 @@ struct Tile {
     const f4* s4 = reinterpret_cast<const f4*>(src);
     f4* d4 = reinterpret_cast<f4*>(sW);
     for (int idx = tid; idx < N4; idx += NT) d4[idx] = s4[idx];
+  }
+
+  // Forward weights alternate between two LDS buffers, sW and the tile buffers
+  // sA/sH (free during the forward, WP x WS + WP <= 2 WP x TPS floats), so
+  // that layer k + 1's weights stream in while layer k computes; the last
+  // hidden layer D always uses sW (the output layer's adjoint stages in sA/sH
+  // right after it).
+  __device__ static float* wbuf(float* sW, int D, int k) {
+    return ((D - k) & 1) ? sW + WP * WS + WP : sW;
+  }
+  __device__ static void fetch_wb(float* dst, const float* K, const Layout& L, int k, int wave, int lane) {
+    dma_to_lds(dst, K + L.k_w(k), WP * WS / 4, wave, lane);
+    dma_to_lds(dst + WP * WS, K + L.k_b(k), WP / 4, wave, lane);
+  }
+  __device__ static void fetch_wt(float* sW, const float* K, const Layout& L, int k, int wave, int lane) {
+    dma_to_lds(sW, K + L.k_wt(k), WP * WS / 4, wave, lane);
   }
 
   // A forward layer's weights and bias go to LDS as [WP][WS] then [WP]: the
@@ -804,6 +834,8 @@ struct Tile {
         sX[tp] = x;
         sX[TP + tp] = y;
       }
+      // the first hidden layer's weights stream in during layer 1
+      if (PHASE != PH_BWD && D >= 2) fetch_wb(wbuf(sW, D, 2), K, L, 2, wave, lane);
 
       // ---- forward: Taylor streams through every layer, stash a^k (in PH_BWD
       // only h^D is rebuilt, from the stashed a^D, or from layer 1 if D = 1)
@@ -821,12 +853,14 @@ struct Tile {
         g = lane >> 4;
         pc = lane & 15;
         tp = wave * 16 + pc;
+        // W^k is in LDS and every wave is done with layer k - 1's buffer,
+        // which now receives W^{k+1}
+        __syncthreads();
+        if (k < D) fetch_wb(wbuf(sW, D, k + 1), K, L, k + 1, wave, lane);
         if constexpr (!RH) stash_store(rs, 1, k - 2, wave, lane, H);   // h^{k-1}
-        __syncthreads();
-        stage_wb(sW, K + L.k_w(k), K + L.k_b(k), tid);
-        __syncthreads();
         Streams Hn;
-        hidden_layer<true, GA>(sW, sW + WP * WS, g, pc, real_steps(nd.width), H, Hn, rs, k - 2, wave, lane,
+        float* wb = wbuf(sW, D, k);
+        hidden_layer<true, GA>(wb, wb + WP * WS, g, pc, real_steps(nd.width), H, Hn, rs, k - 2, wave, lane,
                                nd.act, slope(nd, K, L, k));   // stashes a^k
 #pragma unroll
         for (int st = 0; st < 4; ++st)
@@ -914,6 +948,8 @@ struct Tile {
 #pragma unroll
           for (int i = 0; i < 4; ++i) sB[(16 * mb + 4 * g + i) * TPS + tp] = H[s][mb][i];
         __syncthreads();
+        // every wave is past the last forward layer: W^{D T} streams into sW
+        if (s == 3 && D >= 2) fetch_wt(sW, K, L, D, wave, lane);
 #pragma unroll
         for (int r = 0; r < KL; ++r) {
           const int t = tid + r * NT;
@@ -995,9 +1031,7 @@ struct Tile {
           else layer1(K, x, y, g, Ak);
         }
         Streams& Ab = G;
-        __syncthreads();
-        stage(sW, K + L.k_wt(k), tid);
-        __syncthreads();
+        __syncthreads();   // W^{kT} is in sW (fetched during the previous stage)
         if constexpr (GA) {
           if (nd.adaptive && tid == 0) accum(R + L.g_slope() + k - 1, (sSl[0] + sSl[1]) + (sSl[2] + sSl[3]), first);
         }
@@ -1040,6 +1074,8 @@ struct Tile {
           // a^{k-1} for the next reverse layer, loaded during the last dW^k stream
           if (PREFETCH_A && !RH && s == 3 && k > 2) stash_load(rs, 0, k - 3, wave, lane, Ak);
           __syncthreads();
+          // every wave is done with W^{kT}: W^{(k-1)T} streams in during the last dW^k
+          if (s == 3 && k > 2) fetch_wt(sW, K, L, k - 1, wave, lane);
 #pragma unroll
           for (int r = 0; r < NB; ++r) {
             __builtin_amdgcn_sched_barrier(0);
