@@ -79,6 +79,24 @@ __device__ __forceinline__ void dma_to_lds(float* dst, const float* src, int n4,
   }
 }
 
+// Sum over the 16 lanes of each row (the 16 points of one lane group) with
+// DPP moves: pairs, quads, half rows, rows.  Every lane of the row receives
+// the same (bitwise) sum.
+__device__ __forceinline__ float dpp_add(float v, int ctrl) {
+  switch (ctrl) {   // the control must be a constant
+    case 0xB1: return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false));
+    case 0x4E: return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, false));
+    case 0x141: return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xf, 0xf, false));
+    default: return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xf, 0xf, false));
+  }
+}
+__device__ __forceinline__ float row_sum16(float v) {
+  v = dpp_add(v, 0xB1);    // quad_perm [1, 0, 3, 2]
+  v = dpp_add(v, 0x4E);    // quad_perm [2, 3, 0, 1]
+  v = dpp_add(v, 0x141);   // row_half_mirror
+  return dpp_add(v, 0x140);   // row_mirror
+}
+
 __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -102,28 +120,6 @@ __device__ __forceinline__ float row_sum(const float* a) {
   }
   return acc;
 }
-__device__ __forceinline__ float row_dot(const float* a, const float* b, float acc) {
-#pragma unroll 2
-  for (int p = 0; p < TP; p += 4) {
-    const f4 x = *reinterpret_cast<const f4*>(a + p);
-    const f4 y = *reinterpret_cast<const f4*>(b + p);
-    acc = fmaf(x[0], y[0], fmaf(x[1], y[1], fmaf(x[2], y[2], fmaf(x[3], y[3], acc))));
-  }
-  return acc;
-}
-// sum_p (a[p] * z[p] + h[p])
-__device__ __forceinline__ float row_dot_plus(const float* a, const float* z, const float* h) {
-  float acc = 0.f;
-#pragma unroll 2
-  for (int p = 0; p < TP; p += 4) {
-    const f4 x = *reinterpret_cast<const f4*>(a + p);
-    const f4 y = *reinterpret_cast<const f4*>(z + p);
-    const f4 c = *reinterpret_cast<const f4*>(h + p);
-    acc += fmaf(x[0], y[0], c[0]) + fmaf(x[1], y[1], c[1]) + fmaf(x[2], y[2], c[2]) + fmaf(x[3], y[3], c[3]);
-  }
-  return acc;
-}
-
 template <bool S2>
 __device__ __forceinline__ void tanh_rule(float a, float ax, float ay, float al, float& h, float& hx,
                                           float& hy, float& hl) {
@@ -381,8 +377,6 @@ struct Tile {
   static constexpr int NB = (NBT + kWaves - 1) / kWaves;    // dW blocks per wave
   static constexpr int KL = (DO * WP + NT - 1) / NT;        // output-layer slots per thread
   static constexpr int STASH_LAYER = kWaves * 4 * MB * 1024;  // bytes of one layer's stash
-  // the staged-weight buffer (WP x WS + WP floats) can take a WP x TPS tile
-  static constexpr bool kL1InW = WP * WS + WP >= WP * TPS;
 
   typedef f4 Streams[4][MB];
 
@@ -503,12 +497,16 @@ struct Tile {
     }
   }
 
-  // g^{k-1}_s = W^{kT} abar^k_s for one stream (sW holds W^T)
+  // g^{k-1}_s = W^{kT} abar^k_s for two streams at once (sW holds W^T): each
+  // weight read from LDS feeds two independent MFMA chains
   // (rq as in hidden_layer: padded output neurons of layer k contribute nothing)
-  __device__ static void hidden_bwd_stream(const float* sWT, int g, int pc, int rq, const f4 (&Ab)[MB],
-                                           f4 (&Gs)[MB]) {
+  __device__ static void hidden_bwd_pair(const float* sWT, int g, int pc, int rq, const f4 (&A0)[MB],
+                                         const f4 (&A1)[MB], f4 (&G0)[MB], f4 (&G1)[MB]) {
 #pragma unroll
-    for (int jb = 0; jb < MB; ++jb) Gs[jb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int jb = 0; jb < MB; ++jb) {
+      G0[jb] = f4{0.f, 0.f, 0.f, 0.f};
+      G1[jb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       __builtin_amdgcn_sched_barrier(0);
@@ -518,7 +516,8 @@ struct Tile {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           if (mb == MB - 1 && i >= rq) continue;
-          Gs[jb] = mma(wv[i], Ab[mb][i], Gs[jb]);
+          G0[jb] = mma(wv[i], A0[mb][i], G0[jb]);
+          G1[jb] = mma(wv[i], A1[mb][i], G1[jb]);
         }
       }
     }
@@ -802,9 +801,7 @@ struct Tile {
     float* sW = lds;
     float* sA = sW + WP * WS + WP;   // after the staged weights and bias
     float* sH = sA + WP * TPS;
-    float* sU = sH + WP * TPS;       // [4 streams][3 outputs][TP]
-    float* sX = sU + 4 * 3 * TP;     // [2][TP]
-    float* sRed = sX + 2 * TP;       // [kWaves][kLossTerms]
+    float* sRed = sH + WP * TPS;     // [kWaves][kLossTerms]
     float* sSl = sRed + kWaves * kLossTerms;   // [kWaves] slope-gradient sums
     const int D = nd.depth;
     const Layout L(WP, D, DO);
@@ -830,10 +827,6 @@ struct Tile {
       const float x = valid ? xy[2 * (int64_t)gp] : 0.f;
       const float y = valid ? xy[2 * (int64_t)gp + 1] : 0.f;
       __syncthreads();  // previous tile done with LDS
-      if (g == 0) {
-        sX[tp] = x;
-        sX[TP + tp] = y;
-      }
       // the first hidden layer's weights stream in during layer 1
       if (PHASE != PH_BWD && D >= 2) fetch_wb(wbuf(sW, D, 2), K, L, 2, wave, lane);
 
@@ -894,18 +887,38 @@ struct Tile {
         v += __shfl_xor(v, 8);
         if (lane == 0) sRed[wave * kLossTerms + t] = v;
       }
-      if (g == 0) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int c = 0; c < DO; ++c) sU[(s * 3 + c) * TP + tp] = ub[c][s];
-        if constexpr (MODE == EPI_INV_U) {
+      if constexpr (MODE == EPI_INV_U) {
+        if (g == 0) {
 #pragma unroll
           for (int s = 0; s < 3; ++s) sInv[3 * TP + 3 * tp + s] = kb[s];
         }
       }
 
       // ---- output layer adjoint: g^D = W^{LT} ubar; dW^L, db^L
+      // dW^L[c][n] = sum over points and streams of ubar_c h^D_n and db^L[c] =
+      // sum over points of ubar_c (value stream): each lane's point term, summed
+      // over the wave's 16 points by row_sum16 and over the waves through LDS
+      // (sA is free: the last forward layer used sW)
+      {
+        float* sOut = sA;                      // [kWaves][DO][WP], then [kWaves][DO] bias sums
+        float* sOutB = sA + kWaves * DO * WP;
+#pragma unroll
+        for (int c = 0; c < DO; ++c) {
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              float v = ub[c][0] * H[0][mb][i];
+#pragma unroll
+              for (int st = 1; st < 4; ++st) v = fmaf(ub[c][st], H[st][mb][i], v);
+              v = row_sum16(v);
+              if (pc == 0) sOut[(wave * DO + c) * WP + 16 * mb + 4 * g + i] = v;
+            }
+          }
+          const float vb = row_sum16(ub[c][0]);
+          if (lane == 0) sOutB[wave * DO + c] = vb;
+        }
+      }
       Streams G;
       {
         const float* WL = K + L.k_out();
@@ -930,42 +943,25 @@ struct Tile {
       // (where registers allow; else at the top of each reverse layer)
       Streams Ak;
       if ((PREFETCH_A || RH) && D >= 2) stash_load(rs, 0, D - 2, wave, lane, Ak);
-      float accL[KL];
+      __syncthreads();
+      // every wave is past the last forward layer: W^{D T} streams into sW
+      if (D >= 2) fetch_wt(sW, K, L, D, wave, lane);
 #pragma unroll
       for (int r = 0; r < KL; ++r) {
         const int t = tid + r * NT;
-        accL[r] = t < DO * WP ? prior(R + L.g_out() + t, first) : 0.f;
-      }
-      float accB = tid < DO ? prior(R + L.g_bout() + tid, first) : 0.f;
-      // h^D streams staged alternately in sH and sA (both free here): a buffer
-      // is rewritten two streams later, after every wave has passed the
-      // barrier of the stream in between, so one barrier per stream suffices
+        if (t < DO * WP) {
+          float v = prior(R + L.g_out() + t, first);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        float* sB = (s & 1) ? sA : sH;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) sB[(16 * mb + 4 * g + i) * TPS + tp] = H[s][mb][i];
-        __syncthreads();
-        // every wave is past the last forward layer: W^{D T} streams into sW
-        if (s == 3 && D >= 2) fetch_wt(sW, K, L, D, wave, lane);
-#pragma unroll
-        for (int r = 0; r < KL; ++r) {
-          const int t = tid + r * NT;
-          if (t < DO * WP) {
-            const int c = t / WP, j = t - (t / WP) * WP;
-            accL[r] = row_dot(sU + (s * 3 + c) * TP, sB + j * TPS, accL[r]);
-          }
+          for (int wv = 0; wv < kWaves; ++wv) v += sA[wv * DO * WP + t];
+          R[L.g_out() + t] = v;
         }
-        if (s == 0 && tid < DO) accB += row_sum(sU + tid * TP);
       }
+      if (tid < DO) {
+        float v = prior(R + L.g_bout() + tid, first);
 #pragma unroll
-      for (int r = 0; r < KL; ++r) {
-        const int t = tid + r * NT;
-        if (t < DO * WP) R[L.g_out() + t] = accL[r];
+        for (int wv = 0; wv < kWaves; ++wv) v += sA[kWaves * DO * WP + wv * DO + tid];
+        R[L.g_bout() + tid] = v;
       }
-      if (tid < DO) R[L.g_bout() + tid] = accB;
       if (MODE != EPI_SEED && tid < kLossTerms) {   // the u pass holds a paired item's loss
         float v = 0.f;
         for (int wv = 0; wv < kWaves; ++wv) v += sRed[wv * kLossTerms + tid];
@@ -1040,26 +1036,43 @@ struct Tile {
         // The barrier that frees sA/sH from the previous stream's dW comes after
         // the W^T abar products, which only read sW: a wave that finished its
         // dW blocks early goes on with them.
+        // streams in pairs (0, 1), (2, 3): g^{k-1} of both = W^{kT} abar^k
+        // (one weight read per two MFMAs), then per stream its share of dW^k
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          f4 Hs[MB];
-          if constexpr (RH) {   // h^{k-1}_s = the activation rule on a^{k-1}
-            const float cp = GA ? slope(nd, K, L, k - 1) : 1.f;
+        for (int sp = 0; sp < 2; ++sp) {
+          // h^{k-1} of both streams (stored in the forward), loaded ahead of the
+          // pair's MFMAs so that their latency hides behind them (where the
+          // registers allow: classes up to 64; wider ones load per stream)
+          constexpr bool kEarlyH = WP <= 64;
+          f4 Hp[2][MB];
+          if constexpr (!RH && kEarlyH) {
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                if constexpr (GA)
-                  Hs[mb][i] = act_stream_ga<S2>(s, nd.act, cp, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
-                else
-                  Hs[mb][i] = act_stream<S2>(s, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
-              }
-          } else {
-            stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s (stored in the forward)
+            for (int hh = 0; hh < 2; ++hh) stash_load_stream(rs, 1, k - 2, wave, lane, 2 * sp + hh, Hp[hh]);
           }
-          {
-            f4 Gs[MB];
-            hidden_bwd_stream(sW, g, pc, real_steps(nd.width), Ab[s], Gs);
+          f4 Gp[2][MB];
+          hidden_bwd_pair(sW, g, pc, real_steps(nd.width), Ab[2 * sp], Ab[2 * sp + 1], Gp[0], Gp[1]);
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int s = 2 * sp + hh;
+            f4 Hs[MB];
+            if constexpr (RH) {   // h^{k-1}_s = the activation rule on a^{k-1}
+              const float cp = GA ? slope(nd, K, L, k - 1) : 1.f;
+#pragma unroll
+              for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  if constexpr (GA)
+                    Hs[mb][i] =
+                        act_stream_ga<S2>(s, nd.act, cp, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
+                  else
+                    Hs[mb][i] = act_stream<S2>(s, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
+                }
+            } else if constexpr (kEarlyH) {
+#pragma unroll
+              for (int mb = 0; mb < MB; ++mb) Hs[mb] = Hp[hh][mb];
+            } else {
+              stash_load_stream(rs, 1, k - 2, wave, lane, s, Hs);   // h^{k-1}_s (stored in the forward)
+            }
             if (s > 0) __syncthreads();
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
@@ -1069,29 +1082,29 @@ struct Tile {
                 sH[(16 * mb + 4 * g + i) * TPS + tp] = Hs[mb][i];
               }
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) G[s][mb] = Gs[mb];   // g^{k-1}_s replaces abar^k_s
-          }
-          // a^{k-1} for the next reverse layer, loaded during the last dW^k stream
-          if (PREFETCH_A && !RH && s == 3 && k > 2) stash_load(rs, 0, k - 3, wave, lane, Ak);
-          __syncthreads();
-          // every wave is done with W^{kT}: W^{(k-1)T} streams in during the last dW^k
-          if (s == 3 && k > 2) fetch_wt(sW, K, L, k - 1, wave, lane);
+            for (int mb = 0; mb < MB; ++mb) G[s][mb] = Gp[hh][mb];   // g^{k-1}_s replaces abar^k_s
+            // a^{k-1} for the next reverse layer, loaded during the last dW^k stream
+            if (PREFETCH_A && !RH && s == 3 && k > 2) stash_load(rs, 0, k - 3, wave, lane, Ak);
+            __syncthreads();
+            // every wave is done with W^{kT}: W^{(k-1)T} streams in during the last dW^k
+            if (s == 3 && k > 2) fetch_wt(sW, K, L, k - 1, wave, lane);
 #pragma unroll
-          for (int r = 0; r < NB; ++r) {
-            __builtin_amdgcn_sched_barrier(0);
-            const int b = wave + r * kWaves;
-            if (b < NBT) {
-              const int mb = b / MB, jb = b - (b / MB) * MB;
+            for (int r = 0; r < NB; ++r) {
+              __builtin_amdgcn_sched_barrier(0);
+              const int b = wave + r * kWaves;
+              if (b < NBT) {
+                const int mb = b / MB, jb = b - (b / MB) * MB;
 #pragma unroll
-              for (int gq = 0; gq < TP / 16; ++gq) {
-                const f4 av = *reinterpret_cast<const f4*>(&sA[(16 * mb + pc) * TPS + 16 * gq + 4 * g]);
-                const f4 hv = *reinterpret_cast<const f4*>(&sH[(16 * jb + pc) * TPS + 16 * gq + 4 * g]);
+                for (int gq = 0; gq < TP / 16; ++gq) {
+                  const f4 av = *reinterpret_cast<const f4*>(&sA[(16 * mb + pc) * TPS + 16 * gq + 4 * g]);
+                  const f4 hv = *reinterpret_cast<const f4*>(&sH[(16 * jb + pc) * TPS + 16 * gq + 4 * g]);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dacc[r] = mma(av[i], hv[i], dacc[r]);
+                  for (int i = 0; i < 4; ++i) dacc[r] = mma(av[i], hv[i], dacc[r]);
+                }
               }
             }
+            if (s == 0 && tid < WP) dbias += row_sum(sA + tid * TPS);
           }
-          if (s == 0 && tid < WP) dbias += row_sum(sA + tid * TPS);
         }
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
@@ -1105,7 +1118,10 @@ struct Tile {
         if (tid < WP) R[L.g_b(k) + tid] = dbias;
       }
 
-      // ---- layer 1: abar^1 from a^1 and g^1; dW^1 and db^1 are sums over points
+      // ---- layer 1: abar^1 from a^1 and g^1; dW^1[n] = sum over points of
+      // (abar^1_n z + d abar^1_n) and db^1[n] = sum of abar^1_n: each lane's
+      // point terms, summed over the wave's 16 points by row_sum16 and over
+      // the waves through LDS
       {
         float p0 = 0.f, p1 = 0.f, p2 = 0.f;
         if (tid < WP) {
@@ -1115,9 +1131,10 @@ struct Tile {
         }
         Streams A1;
         layer1(K, x, y, g, A1);
-        __syncthreads();
         const float c1 = GA ? slope(nd, K, L, 1) : 1.f;
         float dc = 0.f;
+        float* sOut = sA;   // [kWaves][3][WP]
+        __syncthreads();    // every wave is done with sA (the last dW, or the output layer's sums)
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -1129,12 +1146,15 @@ struct Tile {
             else
               tanh_adj<S2>(A1[0][mb][i], A1[1][mb][i], A1[2][mb][i], A1[3][mb][i], G[0][mb][i], G[1][mb][i],
                            G[2][mb][i], G[3][mb][i], a0, a1, a2, a3);
-            // abar^1 streams: value to sA, d/dz0 to sH, d/dz1 to sW where the
-            // staged-weight buffer (free in this block) holds WP x TPS floats
-            sA[(16 * mb + 4 * g + i) * TPS + tp] = a0;
-            sH[(16 * mb + 4 * g + i) * TPS + tp] = a1;
-            if constexpr (kL1InW) sW[(16 * mb + 4 * g + i) * TPS + tp] = a2;
-            else G[2][mb][i] = a2;
+            const float r0 = row_sum16(fmaf(a0, x, a1));
+            const float r1 = row_sum16(fmaf(a0, y, a2));
+            const float r2 = row_sum16(a0);
+            if (pc == 0) {
+              const int n = 16 * mb + 4 * g + i;
+              sOut[(wave * 3 + 0) * WP + n] = r0;
+              sOut[(wave * 3 + 1) * WP + n] = r1;
+              sOut[(wave * 3 + 2) * WP + n] = r2;
+            }
           }
         }
         if constexpr (GA) slope_wave_sum(dc, sSl, lane, wave);
@@ -1142,24 +1162,17 @@ struct Tile {
         if constexpr (GA) {
           if (nd.adaptive && tid == 0) accum(R + L.g_slope(), (sSl[0] + sSl[1]) + (sSl[2] + sSl[3]), first);
         }
-        float dw0 = 0.f, dw1 = 0.f, db = 0.f;
         if (tid < WP) {
-          dw0 = row_dot_plus(sA + tid * TPS, sX, sH + tid * TPS);
-          db = row_sum(sA + tid * TPS);
-        }
-        if constexpr (!kL1InW) {
-          __syncthreads();
+          float dw0 = p0, dw1 = p1, db = p2;
 #pragma unroll
-          for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) sH[(16 * mb + 4 * g + i) * TPS + tp] = G[2][mb][i];
-          __syncthreads();
-        }
-        if (tid < WP) {
-          dw1 = row_dot_plus(sA + tid * TPS, sX + TP, (kL1InW ? sW : sH) + tid * TPS);
-          R[4 * tid] = p0 + dw0;
-          R[4 * tid + 1] = p1 + dw1;
-          R[4 * tid + 2] = p2 + db;
+          for (int wv = 0; wv < kWaves; ++wv) {
+            dw0 += sOut[(wv * 3 + 0) * WP + tid];
+            dw1 += sOut[(wv * 3 + 1) * WP + tid];
+            db += sOut[(wv * 3 + 2) * WP + tid];
+          }
+          R[4 * tid] = dw0;
+          R[4 * tid + 1] = dw1;
+          R[4 * tid + 2] = db;
           if (first) R[4 * tid + 3] = 0.f;
         }
       }
@@ -1179,12 +1192,12 @@ struct Tile {
 };
 
 // LDS floats of a train kernel for classes up to WP: the tile buffers of
-// Tile<WP> (sW, sA, sH, sU, sX, sRed, sSl), then the neighbour values sNb (6 per
+// Tile<WP> (sW, sA, sH, sRed, sSl), then the neighbour values sNb (6 per
 // point), then for the inverse problem 9 per point: the own K streams, the K
 // seeds, the neighbour's K streams.
 template <int WP, int PDE>
 constexpr int lds_tile_floats() {
-  return WP * (WP + 4) + WP + 2 * WP * TPS + 4 * 3 * TP + 2 * TP + kWaves * kLossTerms + kWaves;
+  return WP * (WP + 4) + WP + 2 * WP * TPS + kWaves * kLossTerms + kWaves;
 }
 template <int WP, int PDE>
 constexpr int lds_train_floats() {
