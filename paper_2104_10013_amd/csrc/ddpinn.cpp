@@ -83,6 +83,7 @@ struct ddp_problem {
   int blocks_per_cu = 0;         // 0: from the occupancy query
   int items_per_slot = 4;        // work items per resident workgroup the plan aims for
   int recompute = 0;             // activation policy: 1 stash a^k and rebuild h^k in the reverse pass, 0 stash both
+  int concurrent = 0;            // fused step with several train launches: 1 = they run side by side
 
   // plan
   bool planned = false, finalized = false;
@@ -106,6 +107,7 @@ struct ddp_problem {
     int occupancy = 1;       // resident workgroups per CU of that kernel
     int n_slots = 1;
     int64_t slot_floats = 0;
+    int64_t scratch_off = 0;  // first float of the launch's stash slots in the scratch buffer
   };
   std::vector<Launch> launches;
   std::vector<int> t_begin;      // per q ranges (plain path), n_sd + 1
@@ -121,6 +123,8 @@ struct ddp_problem {
   int device = 0;
   hipStream_t stream = nullptr;      // caller's stream
   hipStream_t cap_stream = nullptr;  // private stream used for graph capture
+  hipStream_t side_stream = nullptr; // second stream of concurrent train launches
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int n_slots = 0;
   int64_t slot_floats = 0;
   float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr, *d_kparams = nullptr;
@@ -541,17 +545,29 @@ int enqueue_step(ddp_problem* p, hipStream_t st, int do_adam, float* grad_out, f
   };
   if (b) HIP_TRY(launch_zero_ints(counters, p->n_counters, st));
   if (p->fused) {
+    // concurrent launches (own stash regions): every launch after the first
+    // runs on the side stream, forked from and joined back into st, so a
+    // launch's workgroups take the compute units the other's drained ones free
+    const bool side = !b && p->concurrent && p->launches.size() > 1;
+    if (side) {
+      HIP_TRY(hipEventRecord(p->ev_fork, st));
+      HIP_TRY(hipStreamWaitEvent(p->side_stream, p->ev_fork, 0));
+    }
     for (size_t g = 0; g < p->launches.size(); ++g) {
       const ddp_problem::Launch& l = p->launches[g];
       KArgs ka = make_kargs(p);
       ka.items = p->d_titems + l.begin;
       ka.n_items = l.count;
       ka.counter = counters + g;
-      ka.scratch = scratch;
+      ka.scratch = scratch + (b ? 0 : l.scratch_off);
       ka.scratch_slot = l.slot_floats;
       ka.prologue = g == 0;
       const int grid = std::max(1, std::min(slots_for(l.n_slots, l.slot_floats), l.count));
-      HIP_TRY(launch_train(p->pde, l.wpmax, p->ga, p->recompute, ka, grid, st));
+      HIP_TRY(launch_train(p->pde, l.wpmax, p->ga, p->recompute, ka, grid, side && g > 0 ? p->side_stream : st));
+    }
+    if (side) {
+      HIP_TRY(hipEventRecord(p->ev_join, p->side_stream));
+      HIP_TRY(hipStreamWaitEvent(st, p->ev_join, 0));
     }
     RArgs ra = make_rargs(p);
     reduce_range(p, ra, 0, n_sd);
@@ -600,6 +616,11 @@ void release(ddp_problem* p) {
   p->plan_allocations.clear();
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   p->cap_stream = nullptr;
+  if (p->side_stream) hipStreamDestroy(p->side_stream);
+  p->side_stream = nullptr;
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  if (p->ev_join) hipEventDestroy(p->ev_join);
+  p->ev_fork = p->ev_join = nullptr;
 }
 
 int check_open(const ddp_problem* p) {
@@ -793,6 +814,10 @@ int ddp_set_option(ddp_problem* p, int option, int64_t value) {
       if (value != 0 && value != 1) return fail(DDP_EINVAL, "recompute must be 0 or 1");
       p->recompute = (int)value;
       break;
+    case DDP_OPT_CONCURRENT:
+      if (value != 0 && value != 1) return fail(DDP_EINVAL, "concurrent must be 0 or 1");
+      p->concurrent = (int)value;
+      break;
     default:
       return fail(DDP_EINVAL, "unknown option");
   }
@@ -830,13 +855,24 @@ int install_plan(ddp_problem* p) {
   if (int rc = build_plan(p)) return rc;
   p->slot_floats = scratch_slot_floats(p->pde, p->wpmax, p->recompute);
   int64_t scratch_floats = (int64_t)p->n_slots * p->slot_floats;
+  // sequential launches reuse one stash region; concurrent ones get their own
+  const bool side = p->fused && p->concurrent && p->launches.size() > 1;
+  int64_t side_floats = 0;
   for (ddp_problem::Launch& l : p->launches) {
     HIP_TRY(train_occupancy(p->pde, l.wpmax, p->ga, p->recompute, &l.occupancy));
     if (l.occupancy < 1) return fail(DDP_EHIP, "train kernel cannot be resident (occupancy 0)");
     const int b = p->blocks_per_cu > 0 ? std::min(p->blocks_per_cu, l.occupancy) : l.occupancy;
     l.n_slots = std::max(1, p->n_cu * b);
     l.slot_floats = scratch_slot_floats(p->pde, l.wpmax, p->recompute);
+    l.scratch_off = side ? side_floats : 0;
+    side_floats += (int64_t)l.n_slots * l.slot_floats;
     scratch_floats = std::max(scratch_floats, (int64_t)l.n_slots * l.slot_floats);
+  }
+  if (side) {
+    scratch_floats = std::max(scratch_floats, side_floats);
+    if (!p->side_stream) HIP_TRY(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
+    if (!p->ev_fork) HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    if (!p->ev_join) HIP_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
   }
   // counters: one per fused launch, then one per subdomain (plain path)
   p->n_counters = (int)p->launches.size() + n_sd;
@@ -913,15 +949,16 @@ bool cache_lookup(const char* path, uint64_t sig, int64_t* cfg) {
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
     unsigned long long s = 0;
-    long long c = 0, ips = 0, bpc = 0, rh = 0;
+    long long c = 0, ips = 0, bpc = 0, rh = 0, conc = 0;
     if (std::sscanf(line, "{\"signature\": \"%llx\", \"chunk_points\": %lld, \"items_per_slot\": %lld, "
-                          "\"blocks_per_cu\": %lld, \"recompute\": %lld",
-                    &s, &c, &ips, &bpc, &rh) == 5 &&
+                          "\"blocks_per_cu\": %lld, \"recompute\": %lld, \"concurrent\": %lld",
+                    &s, &c, &ips, &bpc, &rh, &conc) == 6 &&
         s == sig) {
       cfg[0] = c;
       cfg[1] = ips;
       cfg[2] = bpc;
       cfg[3] = rh;
+      cfg[4] = conc;
       found = true;  // the last entry for a signature wins
     }
   }
@@ -979,7 +1016,7 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
   const int ipss[] = {1, 2, 4, 8};
   struct Cand {
     int64_t c;
-    int ips, bpc, rh;
+    int ips, bpc, rh, conc;
     float ms;
   };
   std::vector<Cand> cands;
@@ -990,6 +1027,7 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
     p->items_per_slot = k.ips;
     p->blocks_per_cu = k.bpc;
     p->recompute = k.rh;
+    p->concurrent = k.conc;
     if (int rc = install_plan(p)) return rc;
     if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
     HIP_TRY(hipEventRecord(ev[0], p->stream));
@@ -1005,16 +1043,20 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
     // resident workgroups per CU of this policy's kernels (the fused
     // launches may run narrower kernels than the per-subdomain path)
     p->recompute = rh;
+    p->concurrent = 0;
     if (int rc = install_plan(p)) return rc;
     int max_occ = p->occupancy;
     for (const ddp_problem::Launch& l : p->launches) max_occ = std::max(max_occ, l.occupancy);
-    for (int64_t c : chunks)
-      for (int ips : ipss)
-        for (int bpc = 1; bpc <= max_occ; ++bpc) {
-          Cand k{c, ips, bpc, rh, 0.f};
-          if (int rc = time_cand(k, iters, &k.ms)) return rc;
-          cands.push_back(k);
-        }
+    // side-by-side launches only where the step has more than one
+    const int max_conc = p->fused && p->launches.size() > 1 ? 1 : 0;
+    for (int conc = 0; conc <= max_conc; ++conc)
+      for (int64_t c : chunks)
+        for (int ips : ipss)
+          for (int bpc = 1; bpc <= max_occ; ++bpc) {
+            Cand k{c, ips, bpc, rh, conc, 0.f};
+            if (int rc = time_cand(k, iters, &k.ms)) return rc;
+            cands.push_back(k);
+          }
   }
   // the leading candidates are often within a percent of each other: time the
   // best three again, interleaved over three rounds of 2 x iters passes, and
@@ -1036,6 +1078,7 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
       best[1] = cands[k].ips;
       best[2] = cands[k].bpc;
       best[3] = cands[k].rh;
+      best[4] = cands[k].conc;
     }
   return DDP_OK;
 }
@@ -1046,13 +1089,14 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
   if (int rc = check_final(p)) return rc;
   if (iters < 1) return fail(DDP_EINVAL, "iters must be >= 1");
   const uint64_t sig = problem_signature(p);
-  const int64_t prev[4] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu, p->recompute};
-  int64_t best[4] = {prev[0], prev[1], prev[2], prev[3]};
+  const int64_t prev[5] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu, p->recompute, p->concurrent};
+  int64_t best[5] = {prev[0], prev[1], prev[2], prev[3], prev[4]};
   auto apply = [&](const int64_t* v) {
     p->chunk_points = v[0];
     p->items_per_slot = (int)v[1];
     p->blocks_per_cu = (int)v[2];
     p->recompute = (int)v[3];
+    p->concurrent = (int)v[4];
   };
   // on any failure the previous plan is put back, so the handle stays usable;
   // if even that fails, every later call reports DDP_ESTATE
@@ -1079,9 +1123,9 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
       if (f) {
         std::fprintf(f,
                      "{\"signature\": \"%016llx\", \"chunk_points\": %lld, \"items_per_slot\": %lld, "
-                     "\"blocks_per_cu\": %lld, \"recompute\": %lld, \"ms\": %.5f}\n",
+                     "\"blocks_per_cu\": %lld, \"recompute\": %lld, \"concurrent\": %lld, \"ms\": %.5f}\n",
                      (unsigned long long)sig, (long long)best[0], (long long)best[1], (long long)best[2],
-                     (long long)best[3], best_ms);
+                     (long long)best[3], (long long)best[4], best_ms);
         std::fclose(f);
       }
     }
@@ -1089,7 +1133,7 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
   apply(best);
   if (int rc = install_plan(p)) return restore(rc);
   if (choice)
-    for (int k = 0; k < 4; ++k) choice[k] = best[k];
+    for (int k = 0; k < 5; ++k) choice[k] = best[k];
   return DDP_OK;
 }
 
@@ -1235,18 +1279,27 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
         for (int c = 0; c < p->n_counters; ++c) HIP_TRY(launch_reset_counter(p->d_counters + c, p->stream));
       HIP_TRY(hipEventRecord(ev[0], p->stream));
       if (which == 0) {
+        // as in the step: concurrent launches fork onto the side stream
+        const bool side = p->fused && p->concurrent && p->launches.size() > 1;
+        if (side) {
+          HIP_TRY(hipEventRecord(p->ev_fork, p->stream));
+          HIP_TRY(hipStreamWaitEvent(p->side_stream, p->ev_fork, 0));
+        }
         const int nl = p->fused ? (int)p->launches.size() : n_sd;
         for (int q = 0; q < nl; ++q) {
           KArgs ka = make_kargs(p);
           int wpmax = p->wpmax, n_slots = p->n_slots;
+          hipStream_t st = p->stream;
           if (p->fused) {
             const ddp_problem::Launch& l = p->launches[q];
             ka.items = p->d_titems + l.begin;
             ka.n_items = l.count;
             ka.counter = p->d_counters + q;
+            ka.scratch += l.scratch_off;
             ka.scratch_slot = l.slot_floats;
             wpmax = l.wpmax;
             n_slots = l.n_slots;
+            if (side && q > 0) st = p->side_stream;
           } else {
             ka.items = p->d_titems + p->t_begin[q];
             ka.n_items = p->t_begin[q + 1] - p->t_begin[q];
@@ -1254,7 +1307,11 @@ int ddp_time_kernels(ddp_problem* p, int iters, float* ms) {
           }
           if (ka.n_items == 0) continue;
           const int grid = std::max(1, std::min(n_slots, ka.n_items));
-          HIP_TRY(launch_train(p->pde, wpmax, p->ga, p->recompute, ka, grid, p->stream));
+          HIP_TRY(launch_train(p->pde, wpmax, p->ga, p->recompute, ka, grid, st));
+        }
+        if (side) {
+          HIP_TRY(hipEventRecord(p->ev_join, p->side_stream));
+          HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_join, 0));
         }
       } else {
         RArgs ra = make_rargs(p);
@@ -1341,8 +1398,10 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   if (!p->planned) return fail(DDP_ESTATE, "no plan: call ddp_plan or ddp_finalize first");
   FILE* f = std::fopen(json_path, "w");
   if (!f) return fail(DDP_EINVAL, std::string("cannot open ") + json_path);
-  std::fprintf(f, "{\"method\": %d, \"pde\": %d, \"fused\": %d, \"wpmax\": %d, \"tile_points\": %d, \"recompute\": %d,\n",
-               p->method, p->pde, p->fused, p->wpmax, kTilePts, p->recompute);
+  std::fprintf(f,
+               "{\"method\": %d, \"pde\": %d, \"fused\": %d, \"wpmax\": %d, \"tile_points\": %d, \"recompute\": %d, "
+               "\"concurrent\": %d,\n",
+               p->method, p->pde, p->fused, p->wpmax, kTilePts, p->recompute, p->concurrent);
   std::fprintf(f, "\"nets\": [");
   for (size_t q = 0; q < p->nets.size(); ++q) {
     const NetDesc& n = p->nets[q];

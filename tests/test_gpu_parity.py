@@ -284,7 +284,7 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     pb, lt0, g0 = run(prob)
     cache = tmp_path / "tune.jsonl"
     choice = pb.autotune(iters=2, cache_path=cache)
-    assert choice["recompute"] in (0, 1)
+    assert choice["recompute"] in (0, 1) and choice["concurrent"] in (0, 1)
     assert cache.exists() and len(cache.read_text().splitlines()) == 1
     lt1, g1 = pb.loss_and_grad()
     torch.cuda.synchronize()
@@ -319,6 +319,36 @@ def test_c5_inverse_full_size_bench_launch():
     params = _params(prob, None)
     _say("c5 full size")
     pb, lt, g = run(prob, params)
+    wl, wg = compare(prob, params, lt, g)
+    _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
+    pb.close()
+
+
+def test_concurrent_launches_match_sequential_bitwise():
+    """Items that need the two train kernels (networks up to 80 and wider):
+    the two persistent launches side by side on two streams give the same
+    bits as one after the other, in a loss-and-gradient pass and over graph
+    steps with Adam; full size against the oracle."""
+    prob = W.c5_xpinn_inverse_diffusion(seed=0, scale=0.05)
+    params = _params(prob, 7)
+    out = {}
+    for conc in (0, 1):
+        _say(f"c5 scale 0.05 concurrent {conc}")
+        pb, lt, g = run(prob, params, concurrent=conc)
+        pb.step(3)
+        pb.sync()
+        out[conc] = (lt, g, pb.get_params())
+        pb.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out[0][2], out[1][2]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    compare(prob, params, out[1][0], out[1][1])
+    prob = W.c5_xpinn_inverse_diffusion(seed=0)
+    params = _params(prob, None)
+    _say("c5 full size concurrent 1")
+    pb, lt, g = run(prob, params, concurrent=1)
     wl, wg = compare(prob, params, lt, g)
     _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
     pb.close()
