@@ -40,6 +40,12 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int TP = kTilePts;      // points per tile
 constexpr int TPS = kTilePts + 4; // LDS row stride of staged tiles (floats)
+constexpr int TPS2 = 2 * kTilePts + 4; // row stride of two streams staged side by side
+
+// Widths whose reverse pass stages two streams at once for dW (one pair of
+// barriers per two streams): the doubled staging tiles fit the LDS budget
+// of the widest class up to 48.
+constexpr bool pair_staged(int wp) { return wp <= 48; }
 constexpr int NT = 64 * kWaves;   // threads per workgroup
 
 // One 16-byte-per-lane store into the activation stash, followed by wait
@@ -798,10 +804,14 @@ struct Tile {
   __device__ __forceinline__ static void run_train(const KArgs& ka, const Item& it, const NetDesc& nd, float* lds,
                                    float* slot, int64_t slot_floats, const float* sNb, float* sInv, int t_lo,
                                    int t_hi, int roff) {
+    constexpr bool kPair = pair_staged(WP);
     float* sW = lds;
     float* sA = sW + WP * WS + WP;   // after the staged weights and bias
     float* sH = sA + WP * TPS;
-    float* sRed = sH + WP * TPS;     // [kWaves][kLossTerms]
+    // two streams side by side ([neuron][stream][point], rows of TPS2 floats)
+    // over the same space and beyond it
+    float* sH2 = sA + WP * TPS2;
+    float* sRed = sA + 2 * WP * (kPair ? TPS2 : TPS);   // [kWaves][kLossTerms]
     float* sSl = sRed + kWaves * kLossTerms;   // [kWaves] slope-gradient sums
     const int D = nd.depth;
     const Layout L(WP, D, DO);
@@ -1051,6 +1061,66 @@ struct Tile {
           }
           f4 Gp[2][MB];
           hidden_bwd_pair(sW, g, pc, real_steps(nd.width), Ab[2 * sp], Ab[2 * sp + 1], Gp[0], Gp[1]);
+          if constexpr (kPair) {
+            // both streams of the pair staged at once: dW^k over 2 x 64
+            // (stream, point) terms per barrier pair
+            f4 Hs2[2][MB];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+              const int s = 2 * sp + hh;
+              if constexpr (RH) {
+                const float cp = GA ? slope(nd, K, L, k - 1) : 1.f;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) {
+                    if constexpr (GA)
+                      Hs2[hh][mb][i] =
+                          act_stream_ga<S2>(s, nd.act, cp, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
+                    else
+                      Hs2[hh][mb][i] = act_stream<S2>(s, Ak[0][mb][i], Ak[1][mb][i], Ak[2][mb][i], Ak[3][mb][i]);
+                  }
+              } else {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) Hs2[hh][mb] = Hp[hh][mb];
+              }
+            }
+            if (sp > 0) __syncthreads();
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+              for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  sA[(16 * mb + 4 * g + i) * TPS2 + hh * TP + tp] = Ab[2 * sp + hh][mb][i];
+                  sH2[(16 * mb + 4 * g + i) * TPS2 + hh * TP + tp] = Hs2[hh][mb][i];
+                }
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+              for (int mb = 0; mb < MB; ++mb) G[2 * sp + hh][mb] = Gp[hh][mb];
+            if (PREFETCH_A && !RH && sp == 1 && k > 2) stash_load(rs, 0, k - 3, wave, lane, Ak);
+            __syncthreads();
+            if (sp == 1 && k > 2) fetch_wt(sW, K, L, k - 1, wave, lane);
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+              __builtin_amdgcn_sched_barrier(0);
+              const int b = wave + r * kWaves;
+              if (b < NBT) {
+                const int mb = b / MB, jb = b - (b / MB) * MB;
+#pragma unroll
+                for (int gq = 0; gq < 2 * TP / 16; ++gq) {
+                  const f4 av = *reinterpret_cast<const f4*>(&sA[(16 * mb + pc) * TPS2 + 16 * gq + 4 * g]);
+                  const f4 hv = *reinterpret_cast<const f4*>(&sH2[(16 * jb + pc) * TPS2 + 16 * gq + 4 * g]);
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) dacc[r] = mma(av[i], hv[i], dacc[r]);
+                }
+              }
+            }
+            // db^k from stream 0 (the first half of each row)
+            if (sp == 0 && tid < WP) dbias += row_sum(sA + tid * TPS2);
+            continue;
+          }
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh) {
             const int s = 2 * sp + hh;
@@ -1195,9 +1265,23 @@ struct Tile {
 // Tile<WP> (sW, sA, sH, sRed, sSl), then the neighbour values sNb (6 per
 // point), then for the inverse problem 9 per point: the own K streams, the K
 // seeds, the neighbour's K streams.
+template <int WP>
+constexpr int tile_need_floats() {
+  return WP * (WP + 4) + WP + 2 * WP * (pair_staged(WP) ? TPS2 : TPS) + kWaves * kLossTerms + kWaves;
+}
 template <int WP, int PDE>
 constexpr int lds_tile_floats() {
-  return WP * (WP + 4) + WP + 2 * WP * TPS + kWaves * kLossTerms + kWaves;
+  // the largest need of the classes up to WP (a pair-staged narrow class
+  // can need more than a wider one)
+  int n = 0;
+  if (WP >= 16) n = tile_need_floats<16>();
+  if (WP >= 32) n = n > tile_need_floats<32>() ? n : tile_need_floats<32>();
+  if (WP >= 48) n = n > tile_need_floats<48>() ? n : tile_need_floats<48>();
+  if (WP >= 64) n = n > tile_need_floats<64>() ? n : tile_need_floats<64>();
+  if (WP >= 80) n = n > tile_need_floats<80>() ? n : tile_need_floats<80>();
+  if (WP >= 96) n = n > tile_need_floats<96>() ? n : tile_need_floats<96>();
+  if (WP >= 112) n = n > tile_need_floats<112>() ? n : tile_need_floats<112>();
+  return n;
 }
 template <int WP, int PDE>
 constexpr int lds_train_floats() {
