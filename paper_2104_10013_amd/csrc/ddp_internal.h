@@ -9,6 +9,7 @@ constexpr int kMaxDepth = 8;      // hidden layers
 constexpr int kMaxWidth = 112;    // hidden width
 constexpr int kWaves = 4;         // waves per workgroup
 constexpr int kTilePts = 16 * kWaves;  // points per tile: 16 per wave
+constexpr int kRedParams = 256;  // parameters (threads) per block of the gradient reduction
 constexpr int kLossTerms = 4;     // MSE_u, MSE_F, MSE_uavg, MSE_flux|MSE_R
 
 // point classes of a work item; KIND_AUX = points with known values of the
@@ -142,6 +143,8 @@ struct RArgs {
   const int* sd_loss_ptr;     // n_sd + 1: CSR over subdomains of the loss rows
   const int* loss_rows;       // per CSR entry: loss row
   int net_begin, net_end;     // networks reduced (and updated) by this launch
+  const int* net_blk;         // n_nets + 1: first reduction block of each network (kRedParams a block)
+  const int* blk_net;         // per reduction block: its network
   int sd_begin, sd_end;       // subdomains whose loss terms this launch sums
   float* grad_out;            // gradient output or nullptr
   float* loss_out;            // n_sd x 5 or nullptr

@@ -95,6 +95,7 @@ struct ddp_problem {
   std::vector<int> sd_net;       // n_sd + 1: first network of each subdomain
   std::vector<int64_t> sd_poff;  // n_sd + 1: parameter offsets of subdomains
   std::vector<int64_t> net_poff; // n_nets + 1: parameter offsets of networks
+  std::vector<int> net_blk, blk_net;  // reduction blocks: CSR over networks, and each block's network
   int64_t kparam_floats = 0;
   int plan_slots = 512;          // workgroups the plan balances for
   std::vector<Item> titems;      // train items (fused: descending cost per launch; plain: grouped by q)
@@ -137,6 +138,7 @@ struct ddp_problem {
   float *d_if_xy = nullptr, *d_aux_xy = nullptr, *d_aux_g = nullptr;
   float *d_partial = nullptr, *d_loss_part = nullptr, *d_scratch = nullptr, *d_loss = nullptr;
   int64_t* d_net_poff = nullptr;
+  int *d_net_blk = nullptr, *d_blk_net = nullptr;
   int* d_sd_net = nullptr;
   int *d_net_row_ptr = nullptr, *d_sd_loss_ptr = nullptr, *d_loss_rows = nullptr;
   int64_t* d_row_prow = nullptr;
@@ -267,6 +269,14 @@ int build_plan(ddp_problem* p) {
   }
   p->sd_net[n_sd] = (int)p->nets.size();
   p->wpmax = kernel_wpmax(p->wpmax, p->ga);
+  // the reduction's blocks: kRedParams consecutive parameters of one network each
+  p->net_blk.assign(1, 0);
+  p->blk_net.clear();
+  for (int q = 0; q < (int)p->nets.size(); ++q) {
+    const int nb = (int)((p->net_poff[q + 1] - p->net_poff[q] + kRedParams - 1) / kRedParams);
+    for (int b = 0; b < nb; ++b) p->blk_net.push_back(q);
+    p->net_blk.push_back(p->net_blk.back() + nb);
+  }
 
   // packed point arrays
   p->h_res_xy.clear();
@@ -499,6 +509,8 @@ RArgs make_rargs(ddp_problem* p) {
   ra.loss_part = p->d_loss_part;
   ra.nets = p->d_nets;
   ra.net_poff = p->d_net_poff;
+  ra.net_blk = p->d_net_blk;
+  ra.blk_net = p->d_blk_net;
   ra.net_row_ptr = p->d_net_row_ptr;
   ra.row_prow = p->d_row_prow;
   ra.sd_net = p->d_sd_net;
@@ -518,8 +530,9 @@ void reduce_range(ddp_problem* p, RArgs& ra, int q0, int q1) {
 }
 
 int reduce_grid(ddp_problem* p, int q0, int q1) {
-  const int64_t n = p->sd_poff[q1] - p->sd_poff[q0];
-  return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  // one block per reduction block of the subdomains' networks (block 0 also
+  // sums the loss rows, so at least one)
+  return std::max(1, p->net_blk[p->sd_net[q1]] - p->net_blk[p->sd_net[q0]]);
 }
 
 // Where a step's train launches keep their work counters and activation
@@ -1000,6 +1013,8 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused) {
   if ((rc = dev_upload(p, &p->d_aux_g, p->h_aux_g))) return rc;
   if ((rc = dev_alloc(p, &p->d_loss, (size_t)n_sd * 5))) return rc;
   if ((rc = dev_upload(p, &p->d_net_poff, p->net_poff))) return rc;
+  if ((rc = dev_upload(p, &p->d_net_blk, p->net_blk))) return rc;
+  if ((rc = dev_upload(p, &p->d_blk_net, p->blk_net))) return rc;
   if ((rc = dev_upload(p, &p->d_sd_net, p->sd_net))) return rc;
   if ((rc = install_plan(p))) return rc;
   p->finalized = true;

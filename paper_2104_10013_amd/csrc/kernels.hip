@@ -1480,62 +1480,67 @@ __device__ __forceinline__ int find_net(const int64_t* net_poff, int n, int64_t 
 // kernel-layout copy; the waves of block 0 also sum each subdomain's loss
 // rows and flag non-finite losses.
 //
-// A thread owns one parameter and keeps kRedLanes independent partial sums over
-// the rows (row r goes to sum r mod kRedLanes), combined by a fixed tree: the
-// loads of a batch are independent, and the order does not depend on timing.
+// A block owns kRedParams consecutive parameters of one network, a thread one
+// parameter; it keeps kRedLanes independent partial sums over the rows (row r
+// goes to sum r mod kRedLanes), combined by a fixed tree: the loads of a batch
+// are independent, and the order does not depend on timing.
 constexpr int kRedLanes = 16;
 
-__global__ __launch_bounds__(256) void k_reduce(RArgs ra) {
-  const int64_t p0 = ra.net_poff[ra.net_begin], p1 = ra.net_poff[ra.net_end];
+__global__ __launch_bounds__(kRedParams) void k_reduce(RArgs ra) {
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const float tstep = (float)(ra.tstate[0] + 1);
-  const float bc1 = 1.f - powf(b1, tstep);
-  const float bc2 = 1.f - powf(b2, tstep);
-  for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int q = find_net(ra.net_poff, ra.net_begin, i);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the block's network, its row list and the row offsets are uniform
+  // across the block (scalar loads)
+  const int bidx = ra.net_blk[ra.net_begin] + (int)blockIdx.x;
+  if (bidx < ra.net_blk[ra.net_end]) {
+    const int q = ra.blk_net[bidx];
+    const int64_t i = ra.net_poff[q] + (int64_t)(bidx - ra.net_blk[q]) * kRedParams + threadIdx.x;
     const NetDesc nd = ra.nets[q];
-    int gi, k1, k2;
-    float sc;
-    param_map(nd, (int)(i - ra.net_poff[q]), gi, k1, k2, sc);
     const int r0 = ra.net_row_ptr[q], n = ra.net_row_ptr[q + 1] - r0;
     const int64_t* pr = ra.row_prow + r0;
-    const float* P = ra.partial + gi;
-    float a[kRedLanes];
+    if (i < ra.net_poff[q + 1]) {
+      int gi, k1, k2;
+      float sc;
+      param_map(nd, (int)(i - ra.net_poff[q]), gi, k1, k2, sc);
+      const float* P = ra.partial + gi;
+      float a[kRedLanes];
 #pragma unroll
-    for (int j = 0; j < kRedLanes; ++j) a[j] = 0.f;
-    int r = 0;
-    for (; r + kRedLanes <= n; r += kRedLanes) {
+      for (int j = 0; j < kRedLanes; ++j) a[j] = 0.f;
+      int r = 0;
+      for (; r + kRedLanes <= n; r += kRedLanes) {
 #pragma unroll
-      for (int j = 0; j < kRedLanes; ++j) a[j] += P[pr[r + j]];
-    }
+        for (int j = 0; j < kRedLanes; ++j) a[j] += P[pr[r + j]];
+      }
 #pragma unroll
-    for (int j = 0; j < kRedLanes; ++j)
-      if (r + j < n) a[j] += P[pr[r + j]];
+      for (int j = 0; j < kRedLanes; ++j)
+        if (r + j < n) a[j] += P[pr[r + j]];
 #pragma unroll
-    for (int w = kRedLanes / 2; w >= 1; w /= 2)
+      for (int w = kRedLanes / 2; w >= 1; w /= 2)
 #pragma unroll
-      for (int j = 0; j < w; ++j) a[j] += a[j + w];
-    const float s = sc * a[0];
-    if (ra.grad_out) ra.grad_out[i] = s;
-    if (ra.do_adam) {
-      const float m = b1 * ra.adam_m[i] + (1.f - b1) * s;
-      const float v = b2 * ra.adam_v[i] + (1.f - b2) * s * s;
-      ra.adam_m[i] = m;
-      ra.adam_v[i] = v;
-      const float mh = m / bc1;
-      const float vh = v / bc2;
-      const float th = ra.params[i] - nd.lr * mh / (sqrtf(vh) + eps);
-      ra.params[i] = th;
-      float* K = ra.kparams + nd.koff;
-      K[k1] = sc * th;
-      if (k2 >= 0) K[k2] = th;
+        for (int j = 0; j < w; ++j) a[j] += a[j + w];
+      const float s = sc * a[0];
+      if (ra.grad_out) ra.grad_out[i] = s;
+      if (ra.do_adam) {
+        const float tstep = (float)(ra.tstate[0] + 1);
+        const float bc1 = 1.f - powf(b1, tstep);
+        const float bc2 = 1.f - powf(b2, tstep);
+        const float m = b1 * ra.adam_m[i] + (1.f - b1) * s;
+        const float v = b2 * ra.adam_v[i] + (1.f - b2) * s * s;
+        ra.adam_m[i] = m;
+        ra.adam_v[i] = v;
+        const float mh = m / bc1;
+        const float vh = v / bc2;
+        const float th = ra.params[i] - nd.lr * mh / (sqrtf(vh) + eps);
+        ra.params[i] = th;
+        float* K = ra.kparams + nd.koff;
+        K[k1] = sc * th;
+        if (k2 >= 0) K[k2] = th;
+      }
     }
   }
   if (blockIdx.x == 0) {
     // one wave per subdomain: lane l sums rows l, l + 64, ...; then a fixed
     // butterfly across the wave
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int q = ra.sd_begin + wave; q < ra.sd_end; q += (int)(blockDim.x >> 6)) {
       float t[kLossTerms] = {0.f, 0.f, 0.f, 0.f};
       for (int r = ra.sd_loss_ptr[q] + lane; r < ra.sd_loss_ptr[q + 1]; r += 64) {
@@ -1772,7 +1777,7 @@ hipError_t launch_reset_counter(int* c, hipStream_t st) {
 }
 
 hipError_t launch_reduce(const RArgs& ra, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, st, ra);
+  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(kRedParams), 0, st, ra);
   return hipGetLastError();
 }
 
