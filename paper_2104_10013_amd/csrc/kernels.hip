@@ -74,8 +74,10 @@ __device__ __forceinline__ int item_tid() {
 // Asynchronous copy of n4 float4 (16-byte aligned at both ends) from global
 // memory straight into LDS (gfx950 LDS DMA, no registers): wave `wave`
 // copies the 1 KB blocks wave, wave + kWaves, ...; lane l of a block moves
-// its 16 bytes to block base + 16 l.  The data is complete at the next
-// workgroup barrier (the compiler waits on the load counter there).
+// its 16 bytes to block base + 16 l.  A wave's copies are counted by its
+// vector-memory counter; the compiler waits on it only before that wave's own
+// LDS reads, so the barrier that hands the buffer to the other waves must be
+// preceded by dma_landed() in every wave.
 __device__ __forceinline__ void dma_to_lds(float* dst, const float* src, int n4, int wave, int lane) {
   for (int b = wave; b * 64 < n4; b += kWaves) {
     const int c = b * 64 + lane;
@@ -84,6 +86,11 @@ __device__ __forceinline__ void dma_to_lds(float* dst, const float* src, int n4,
                                        0);
   }
 }
+
+// Wait until every vector-memory operation of this wave has completed
+// (s_waitcnt vmcnt(0), the other counters left alone), so its LDS DMA copies
+// have landed; gfx950 does not wait for them at a barrier by itself.
+__device__ __forceinline__ void dma_landed() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Sum over the 16 lanes of each row (the 16 points of one lane group) with
 // DPP moves: pairs, quads, half rows, rows.  Every lane of the row receives
@@ -856,8 +863,9 @@ struct Tile {
         g = lane >> 4;
         pc = lane & 15;
         tp = wave * 16 + pc;
-        // W^k is in LDS and every wave is done with layer k - 1's buffer,
-        // which now receives W^{k+1}
+        // W^k is in LDS (every wave's share landed) and every wave is done
+        // with layer k - 1's buffer, which now receives W^{k+1}
+        dma_landed();
         __syncthreads();
         if (k < D) fetch_wb(wbuf(sW, D, k + 1), K, L, k + 1, wave, lane);
         if constexpr (!RH) stash_store(rs, 1, k - 2, wave, lane, H);   // h^{k-1}
@@ -1037,6 +1045,7 @@ struct Tile {
           else layer1(K, x, y, g, Ak);
         }
         Streams& Ab = G;
+        dma_landed();
         __syncthreads();   // W^{kT} is in sW (fetched during the previous stage)
         if constexpr (GA) {
           if (nd.adaptive && tid == 0) accum(R + L.g_slope() + k - 1, (sSl[0] + sSl[1]) + (sSl[2] + sSl[3]), first);
