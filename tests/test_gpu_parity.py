@@ -738,3 +738,31 @@ def test_recompute_policy(name, scale):
                 wl, wg = compare(prob, params, lt, g, ref=ref)
                 _say(f"  worst loss rel {wl:.2e} grad rel {wg:.2e}")
                 pb.close()
+
+
+@pytest.mark.parametrize("name,scale,seed", [("c2_xpinn_poisson", 0.1, 1), ("burgers_st_xpinn_2x2", 0.2, 0),
+                                             ("c5_xpinn_inverse_diffusion", 0.03, 0)])
+def test_work_plans_against_oracle(name, scale, seed):
+    """The work plans the autotuner chooses among (points per item, items per
+    workgroup, workgroups per CU, activation policy, and for the inverse problem
+    side-by-side launches) all give the oracle's loss and gradient."""
+    prob = W.make_problem(name, seed=seed, scale=scale)
+    params = _params(prob, 3)
+    ref = oracle.loss_and_grad(prob, params)
+    conc = (0, 1) if name.startswith("c5") else (0,)
+    worst = 0.0
+    for chunk in (64, 512, 4096):
+        for ips in (1, 8):
+            for bpc in (1, 2):
+                for rh in (0, 1):
+                    for cc in conc:
+                        pb, lt, g = run(prob, params, chunk_points=chunk, items_per_slot=ips, blocks_per_cu=bpc,
+                                        recompute=rh, concurrent=cc)
+                        try:
+                            wl, wg = compare(prob, params, lt, g, ref=ref)
+                        except AssertionError:
+                            _say(f"{name} plan {chunk}/{ips}/{bpc}/rh{rh}/c{cc} failed")
+                            raise
+                        worst = max(worst, wl, wg)
+                        pb.close()
+    _say(f"{name}: every plan within the bar, worst {worst:.2e}")
