@@ -86,11 +86,15 @@ enum {
   DDP_OPT_RECOMPUTE = 3, /* activation stash policy (default 0): 1 = the forward pass stores the
                            pre-activation streams a^k only and the reverse pass rebuilds h^k from
                            them with the activation rule; 0 = it stores a^k and h^k */
-  DDP_OPT_CONCURRENT = 4 /* fused step whose items need two train kernels (networks both at most
+  DDP_OPT_CONCURRENT = 4, /* fused step whose items need two train kernels (networks both at most
                             80 and wider than 80): 1 = the two persistent launches run side by
                             side on two streams (each with its own activation stash), so the
                             second takes the compute units the first's drained workgroups free;
                             0 (default) = one after the other.  No effect with one launch. */
+  DDP_OPT_TAIL = 5 /* fused step: percent (0..100, default 0) of each subdomain's residual points
+                      cut into one-tile (64-point) work items instead of the plan's longer ones;
+                      the cost-ordered work queue hands them out last, so the workgroups that
+                      finish their long items early share the end of the launch */
 };
 
 /* Create an empty problem.  coef holds n_coef operator constants (see the
@@ -170,16 +174,17 @@ int ddp_finalize(ddp_problem* p, void* hip_stream, int fused);
 /* Autotuner: time candidate work plans on this problem (points per item
  * bound 256..2048, items per resident workgroup 1..8, workgroups per compute
  * unit 1..as many as fit, both activation stash policies of
- * DDP_OPT_RECOMPUTE, and where the step has two train launches both settings
- * of DDP_OPT_CONCURRENT) with iters loss-and-gradient passes each, time the
+ * DDP_OPT_RECOMPUTE, where the step has two train launches both settings
+ * of DDP_OPT_CONCURRENT, and on the fused path a tail share DDP_OPT_TAIL of 0
+ * or 30 percent) with iters loss-and-gradient passes each, time the
  * three fastest again (three interleaved rounds of 2 x iters passes), keep the
  * fastest and rebuild the step graph with it.  Parameters and Adam state are
  * not changed.  cache_path (may be NULL) is a JSON-lines file of earlier
  * choices keyed by a signature of the problem (operator, interface methods, fused or
  * per-subdomain path, widths, depths, point counts, CU count): a hit skips
  * the search, a miss appends the new choice.  choice (may be NULL) receives
- * the 5 chosen values (points per item, items per workgroup, workgroups per
- * compute unit, recompute policy, concurrent launches).  Not safe to call while the caller's stream runs other
+ * the 6 chosen values (points per item, items per workgroup, workgroups per
+ * compute unit, recompute policy, concurrent launches, tail share).  Not safe to call while the caller's stream runs other
  * work on this problem. */
 int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* choice);
 

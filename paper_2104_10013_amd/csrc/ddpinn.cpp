@@ -84,6 +84,7 @@ struct ddp_problem {
   int items_per_slot = 4;        // work items per resident workgroup the plan aims for
   int recompute = 0;             // activation policy: 1 stash a^k and rebuild h^k in the reverse pass, 0 stash both
   int concurrent = 0;            // fused step with several train launches: 1 = they run side by side
+  int tail_pct = 0;              // percent of each subdomain's residual points in one-tile items
 
   // plan
   bool planned = false, finalized = false;
@@ -347,17 +348,26 @@ int build_plan(ddp_problem* p) {
   auto add_chunks = [&](int q, int net, int kind, int begin, int count, int iface, int side, float inv_n) {
     // interface items are one tile: the neighbour's network is evaluated on
     // the same tile first
+    // With a tail share, the last tail_pct percent of a subdomain's residual
+    // points go into one-tile items, which the cost-ordered queue hands out
+    // last: workgroups that finish their long items early share the end.
     const int64_t chunk = kind == KIND_IFACE ? kTilePts : chunk_q[q];
-    for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+    int64_t tail = 0;
+    if (kind == KIND_RES && p->fused && p->tail_pct > 0)
+      tail = std::min<int64_t>(count, ((int64_t)count * p->tail_pct / 100 + kTilePts - 1) / kTilePts * kTilePts);
+    const int64_t bulk = count - tail;
+    for (int64_t c0 = 0; c0 < count;) {
+      const int64_t len = c0 < bulk ? std::min<int64_t>(chunk, bulk - c0) : std::min<int64_t>(kTilePts, count - c0);
       Item it{};
       it.q = net;
       it.kind = kind;
       it.begin = begin + (int)c0;
-      it.count = (int)std::min<int64_t>(chunk, count - c0);
+      it.count = (int)len;
       it.iface = iface;
       it.side = side;
       it.inv_n = inv_n;
       per_q[q].push_back(it);
+      c0 += len;
     }
   };
   for (int q = 0; q < n_sd; ++q) {
@@ -831,6 +841,10 @@ int ddp_set_option(ddp_problem* p, int option, int64_t value) {
       if (value != 0 && value != 1) return fail(DDP_EINVAL, "concurrent must be 0 or 1");
       p->concurrent = (int)value;
       break;
+    case DDP_OPT_TAIL:
+      if (value < 0 || value > 100) return fail(DDP_EINVAL, "tail share must be 0..100 percent");
+      p->tail_pct = (int)value;
+      break;
     default:
       return fail(DDP_EINVAL, "unknown option");
   }
@@ -962,16 +976,17 @@ bool cache_lookup(const char* path, uint64_t sig, int64_t* cfg) {
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {
     unsigned long long s = 0;
-    long long c = 0, ips = 0, bpc = 0, rh = 0, conc = 0;
+    long long c = 0, ips = 0, bpc = 0, rh = 0, conc = 0, tail = 0;
     if (std::sscanf(line, "{\"signature\": \"%llx\", \"chunk_points\": %lld, \"items_per_slot\": %lld, "
-                          "\"blocks_per_cu\": %lld, \"recompute\": %lld, \"concurrent\": %lld",
-                    &s, &c, &ips, &bpc, &rh, &conc) == 6 &&
+                          "\"blocks_per_cu\": %lld, \"recompute\": %lld, \"concurrent\": %lld, \"tail\": %lld",
+                    &s, &c, &ips, &bpc, &rh, &conc, &tail) == 7 &&
         s == sig) {
       cfg[0] = c;
       cfg[1] = ips;
       cfg[2] = bpc;
       cfg[3] = rh;
       cfg[4] = conc;
+      cfg[5] = tail;
       found = true;  // the last entry for a signature wins
     }
   }
@@ -1031,7 +1046,7 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
   const int ipss[] = {1, 2, 4, 8};
   struct Cand {
     int64_t c;
-    int ips, bpc, rh, conc;
+    int ips, bpc, rh, conc, tail;
     float ms;
   };
   std::vector<Cand> cands;
@@ -1043,6 +1058,7 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
     p->blocks_per_cu = k.bpc;
     p->recompute = k.rh;
     p->concurrent = k.conc;
+    p->tail_pct = k.tail;
     if (int rc = install_plan(p)) return rc;
     if (int rc = enqueue_step(p, p->stream, 0, nullptr, p->d_loss)) return rc;
     HIP_TRY(hipEventRecord(ev[0], p->stream));
@@ -1059,19 +1075,24 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
     // launches may run narrower kernels than the per-subdomain path)
     p->recompute = rh;
     p->concurrent = 0;
+    p->tail_pct = 0;
     if (int rc = install_plan(p)) return rc;
     int max_occ = p->occupancy;
     for (const ddp_problem::Launch& l : p->launches) max_occ = std::max(max_occ, l.occupancy);
     // side-by-side launches only where the step has more than one
     const int max_conc = p->fused && p->launches.size() > 1 ? 1 : 0;
+    // a tail share of one-tile items only on the fused path
+    const int tails[2] = {0, 30};
+    const int n_tails = p->fused ? 2 : 1;
     for (int conc = 0; conc <= max_conc; ++conc)
-      for (int64_t c : chunks)
-        for (int ips : ipss)
-          for (int bpc = 1; bpc <= max_occ; ++bpc) {
-            Cand k{c, ips, bpc, rh, conc, 0.f};
-            if (int rc = time_cand(k, iters, &k.ms)) return rc;
-            cands.push_back(k);
-          }
+      for (int t = 0; t < n_tails; ++t)
+        for (int64_t c : chunks)
+          for (int ips : ipss)
+            for (int bpc = 1; bpc <= max_occ; ++bpc) {
+              Cand k{c, ips, bpc, rh, conc, tails[t], 0.f};
+              if (int rc = time_cand(k, iters, &k.ms)) return rc;
+              cands.push_back(k);
+            }
   }
   // the leading candidates are often within a percent of each other: time the
   // best three again, interleaved over three rounds of 2 x iters passes, and
@@ -1094,6 +1115,7 @@ int autotune_search(ddp_problem* p, int iters, hipEvent_t* ev, int64_t* best, fl
       best[2] = cands[k].bpc;
       best[3] = cands[k].rh;
       best[4] = cands[k].conc;
+      best[5] = cands[k].tail;
     }
   return DDP_OK;
 }
@@ -1104,14 +1126,16 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
   if (int rc = check_final(p)) return rc;
   if (iters < 1) return fail(DDP_EINVAL, "iters must be >= 1");
   const uint64_t sig = problem_signature(p);
-  const int64_t prev[5] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu, p->recompute, p->concurrent};
-  int64_t best[5] = {prev[0], prev[1], prev[2], prev[3], prev[4]};
+  const int64_t prev[6] = {p->chunk_points, p->items_per_slot, p->blocks_per_cu,
+                           p->recompute,   p->concurrent,     p->tail_pct};
+  int64_t best[6] = {prev[0], prev[1], prev[2], prev[3], prev[4], prev[5]};
   auto apply = [&](const int64_t* v) {
     p->chunk_points = v[0];
     p->items_per_slot = (int)v[1];
     p->blocks_per_cu = (int)v[2];
     p->recompute = (int)v[3];
     p->concurrent = (int)v[4];
+    p->tail_pct = (int)v[5];
   };
   // on any failure the previous plan is put back, so the handle stays usable;
   // if even that fails, every later call reports DDP_ESTATE
@@ -1138,9 +1162,10 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
       if (f) {
         std::fprintf(f,
                      "{\"signature\": \"%016llx\", \"chunk_points\": %lld, \"items_per_slot\": %lld, "
-                     "\"blocks_per_cu\": %lld, \"recompute\": %lld, \"concurrent\": %lld, \"ms\": %.5f}\n",
+                     "\"blocks_per_cu\": %lld, \"recompute\": %lld, \"concurrent\": %lld, \"tail\": %lld, "
+                     "\"ms\": %.5f}\n",
                      (unsigned long long)sig, (long long)best[0], (long long)best[1], (long long)best[2],
-                     (long long)best[3], (long long)best[4], best_ms);
+                     (long long)best[3], (long long)best[4], (long long)best[5], best_ms);
         std::fclose(f);
       }
     }
@@ -1148,7 +1173,7 @@ int ddp_autotune(ddp_problem* p, int iters, const char* cache_path, int64_t* cho
   apply(best);
   if (int rc = install_plan(p)) return restore(rc);
   if (choice)
-    for (int k = 0; k < 5; ++k) choice[k] = best[k];
+    for (int k = 0; k < 6; ++k) choice[k] = best[k];
   return DDP_OK;
 }
 
@@ -1415,8 +1440,8 @@ int ddp_plan_dump(const ddp_problem* p, const char* json_path) {
   if (!f) return fail(DDP_EINVAL, std::string("cannot open ") + json_path);
   std::fprintf(f,
                "{\"method\": %d, \"pde\": %d, \"fused\": %d, \"wpmax\": %d, \"tile_points\": %d, \"recompute\": %d, "
-               "\"concurrent\": %d,\n",
-               p->method, p->pde, p->fused, p->wpmax, kTilePts, p->recompute, p->concurrent);
+               "\"concurrent\": %d, \"tail\": %d,\n",
+               p->method, p->pde, p->fused, p->wpmax, kTilePts, p->recompute, p->concurrent, p->tail_pct);
   std::fprintf(f, "\"nets\": [");
   for (size_t q = 0; q < p->nets.size(); ++q) {
     const NetDesc& n = p->nets[q];

@@ -21,7 +21,8 @@ DDP_OK, DDP_EINVAL, DDP_ENOMEM, DDP_EHIP, DDP_ESTATE, DDP_ENONFINITE = 0, -1, -2
 DDP_CPINN, DDP_XPINN = 0, 1
 DDP_POISSON2D, DDP_BURGERS1D, DDP_NS2D_STEADY, DDP_DIFFUSION2D_INV = 0, 1, 2, 3
 DDP_RESIDUAL, DDP_DATA, DDP_DATA_AUX = 0, 1, 2
-DDP_OPT_CHUNK_POINTS, DDP_OPT_BLOCKS_PER_CU, DDP_OPT_ITEMS_PER_SLOT, DDP_OPT_RECOMPUTE, DDP_OPT_CONCURRENT = 0, 1, 2, 3, 4
+(DDP_OPT_CHUNK_POINTS, DDP_OPT_BLOCKS_PER_CU, DDP_OPT_ITEMS_PER_SLOT, DDP_OPT_RECOMPUTE, DDP_OPT_CONCURRENT,
+ DDP_OPT_TAIL) = 0, 1, 2, 3, 4, 5
 DDP_ACT_TANH, DDP_ACT_SIN, DDP_ACT_COS = 0, 1, 2
 _ACT = {"tanh": DDP_ACT_TANH, "sin": DDP_ACT_SIN, "cos": DDP_ACT_COS}
 
@@ -127,7 +128,8 @@ class Problem:
     HIP graph.  fused=False: the same kernels launched per subdomain."""
 
     def __init__(self, prob: W.Problem, fused=True, device="cuda", stream=None, chunk_points=None,
-                 blocks_per_cu=None, items_per_slot=None, recompute=None, concurrent=None, plan_only=False):
+                 blocks_per_cu=None, items_per_slot=None, recompute=None, concurrent=None, tail=None,
+                 plan_only=False):
         L = load_library()
         self.prob = prob
         self.fused = bool(fused)
@@ -175,6 +177,8 @@ class Problem:
                 _check(L.ddp_set_option(self._h, DDP_OPT_RECOMPUTE, int(recompute)))
             if concurrent is not None:
                 _check(L.ddp_set_option(self._h, DDP_OPT_CONCURRENT, int(concurrent)))
+            if tail is not None:
+                _check(L.ddp_set_option(self._h, DDP_OPT_TAIL, int(tail)))
             self.n_params = []
             for q in range(self.n_sd):
                 n = ctypes.c_int64()
@@ -283,11 +287,11 @@ class Problem:
 
     def autotune(self, iters=5, cache_path=None):
         """Pick the fastest work plan (see ddp_autotune); returns the choice."""
-        ch = (ctypes.c_int64 * 5)()
+        ch = (ctypes.c_int64 * 6)()
         path = None if cache_path is None else str(cache_path).encode()
         _check(_lib.ddp_autotune(self._h, int(iters), path, ch))
         return {"chunk_points": ch[0], "items_per_slot": ch[1], "blocks_per_cu": ch[2], "recompute": ch[3],
-                "concurrent": ch[4]}
+                "concurrent": ch[4], "tail": ch[5]}
 
     def plan_dump(self, path):
         _check(_lib.ddp_plan_dump(self._h, str(path).encode()))

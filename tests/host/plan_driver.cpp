@@ -150,6 +150,8 @@ static void validation() {
   EXPECT(ddp_set_option(p, DDP_OPT_RECOMPUTE, 0), DDP_OK);
   EXPECT(ddp_set_option(p, DDP_OPT_CONCURRENT, -1), DDP_EINVAL);
   EXPECT(ddp_set_option(p, DDP_OPT_CONCURRENT, 1), DDP_OK);
+  EXPECT(ddp_set_option(p, DDP_OPT_TAIL, 101), DDP_EINVAL);
+  EXPECT(ddp_set_option(p, DDP_OPT_TAIL, 30), DDP_OK);
   EXPECT(ddp_mfma_probe(0, nullptr), DDP_EINVAL);
   EXPECT(ddp_plan(p), DDP_OK);
   EXPECT(ddp_plan_dump(p, "/nonexistent-dir/x.json"), DDP_EINVAL);

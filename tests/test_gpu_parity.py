@@ -284,7 +284,7 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     pb, lt0, g0 = run(prob)
     cache = tmp_path / "tune.jsonl"
     choice = pb.autotune(iters=2, cache_path=cache)
-    assert choice["recompute"] in (0, 1) and choice["concurrent"] in (0, 1)
+    assert choice["recompute"] in (0, 1) and choice["concurrent"] in (0, 1) and choice["tail"] in (0, 30)
     assert cache.exists() and len(cache.read_text().splitlines()) == 1
     lt1, g1 = pb.loss_and_grad()
     torch.cuda.synchronize()
@@ -744,8 +744,9 @@ def test_recompute_policy(name, scale):
                                              ("c5_xpinn_inverse_diffusion", 0.03, 0)])
 def test_work_plans_against_oracle(name, scale, seed):
     """The work plans the autotuner chooses among (points per item, items per
-    workgroup, workgroups per CU, activation policy, and for the inverse problem
-    side-by-side launches) all give the oracle's loss and gradient."""
+    workgroup, workgroups per CU, activation policy, tail share of one-tile
+    items, and for the inverse problem side-by-side launches) all give the
+    oracle's loss and gradient."""
     prob = W.make_problem(name, seed=seed, scale=scale)
     params = _params(prob, 3)
     ref = oracle.loss_and_grad(prob, params)
@@ -756,8 +757,9 @@ def test_work_plans_against_oracle(name, scale, seed):
             for bpc in (1, 2):
                 for rh in (0, 1):
                     for cc in conc:
+                        tail = 30 if (ips == 8) == (rh == 1) else 0
                         pb, lt, g = run(prob, params, chunk_points=chunk, items_per_slot=ips, blocks_per_cu=bpc,
-                                        recompute=rh, concurrent=cc)
+                                        recompute=rh, concurrent=cc, tail=tail)
                         try:
                             wl, wg = compare(prob, params, lt, g, ref=ref)
                         except AssertionError:
